@@ -1,0 +1,707 @@
+// FP64 CPU oracle for the relativistic lattice Boltzmann (RLB) model of
+// Q. Li, K. H. Luo and X. J. Li, "Lattice Boltzmann method for relativistic
+// hydrodynamics: issues on conservation law of particle number and
+// discontinuities" (arXiv:1211.3286).
+//
+// TEST INFRASTRUCTURE ONLY. This library is loaded by the test-suite, by the
+// package smoke check and by the CPU-baseline leg of the benchmark, and by
+// nothing else. The GPU library shares no code, header, table or constant with
+// it: the lattice, the moment basis and its inverse are built here on their own.
+//
+// What it computes, step by step in the paper's notation (all in double):
+//   * D3Q19 velocities e_a, weights w_a, c_s^2 = 1/3, c = dx/dt = 1 (Sec. II).
+//   * f_eq (Eq. 7), g_eq (Eqs. 8-9), moments n*gamma, sigma - P, sigma*u (Eq. 10).
+//   * Recovery of (n, eps, P, gamma, u) from the three moments of Eq. (10)
+//     with the equation of state P = eps/3, as the subluminal root of the
+//     quadratic that Eq. (10) gives for |u|.
+//   * f collision: BGK, Eq. (5).
+//   * g collision: MRT, Eqs. (30), (31), (35): m = M g, m_eq = M g_eq,
+//     m* = m - S (m - m_eq), g* = M^-1 m*, with tau_sigma = tau_j = dt for the
+//     conserved rows. M is the orthogonal D3Q19 polynomial basis (the paper
+//     prints only the D2Q9 case, Eq. 34); M^-1 is formed by Gauss-Jordan.
+//   * Streaming: g(x + e_a, t + 1) = g*(x, t) (left side of Eqs. 5, 6, 35),
+//     written as a pull with periodic wrap or zero-gradient clamp per axis.
+//   * Adjoint of the g update (recovery, equilibria, MRT, streaming) by
+//     complex-step Jacobians of the very same per-cell code.
+//
+// Readings where the paper is silent are listed in the design notes; each one
+// used here is named at its place in the code.
+
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+typedef std::complex<double> cplx;
+
+// ---------------------------------------------------------------------------
+// Lattice (Sec. II, D3Q19). Ordering: rest, six faces, twelve edges; opposite
+// directions are neighbours in the list. The weights are not printed in the
+// paper: 1/3, 1/18, 1/36 are the D3Q19 weights with c_s^2 = 1/3.
+// ---------------------------------------------------------------------------
+const int EV[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1}, {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+const double CS2 = 1.0 / 3.0;
+
+double WV[19];
+double MM[19][19];    // moment basis, row k = polynomial k evaluated at e_a
+double MINV[19][19];  // its inverse
+double NORM[19];      // squared row norms
+bool tables_ready = false;
+
+// Row polynomials of the orthogonal D3Q19 basis of d'Humieres et al. (2002):
+// rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww,
+// p_xy, p_yz, p_xz, m_x, m_y, m_z.
+double basis_poly(int k, double x, double y, double z) {
+  double r2 = x * x + y * y + z * z;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return 19.0 * r2 - 30.0;
+    case 2: return (21.0 * r2 * r2 - 53.0 * r2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * r2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * r2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * r2 - 9.0) * z;
+    case 9: return 3.0 * x * x - r2;
+    case 10: return (3.0 * r2 - 5.0) * (3.0 * x * x - r2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * r2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    case 18: return (x * x - y * y) * z;
+  }
+  return 0.0;
+}
+
+// Gauss-Jordan inverse with partial pivoting of an n x n row-major matrix.
+void invert(int n, const double* A, double* Ainv) {
+  std::vector<double> a(A, A + n * n);
+  for (int i = 0; i < n * n; ++i) Ainv[i] = 0.0;
+  for (int i = 0; i < n; ++i) Ainv[i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(a[r * n + c]) > std::fabs(a[p * n + c])) p = r;
+    if (p != c)
+      for (int j = 0; j < n; ++j) {
+        std::swap(a[p * n + j], a[c * n + j]);
+        std::swap(Ainv[p * n + j], Ainv[c * n + j]);
+      }
+    double d = a[c * n + c];
+    for (int j = 0; j < n; ++j) {
+      a[c * n + j] /= d;
+      Ainv[c * n + j] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      double f = a[r * n + c];
+      if (f == 0.0) continue;
+      for (int j = 0; j < n; ++j) {
+        a[r * n + j] -= f * a[c * n + j];
+        Ainv[r * n + j] -= f * Ainv[c * n + j];
+      }
+    }
+  }
+}
+
+void build_tables() {
+  if (tables_ready) return;
+  for (int a = 0; a < 19; ++a) {
+    int r2 = EV[a][0] * EV[a][0] + EV[a][1] * EV[a][1] + EV[a][2] * EV[a][2];
+    WV[a] = (r2 == 0) ? 1.0 / 3.0 : (r2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  for (int k = 0; k < 19; ++k) {
+    NORM[k] = 0.0;
+    for (int a = 0; a < 19; ++a) {
+      MM[k][a] = basis_poly(k, EV[a][0], EV[a][1], EV[a][2]);
+      NORM[k] += MM[k][a] * MM[k][a];
+    }
+  }
+  invert(19, &MM[0][0], &MINV[0][0]);
+  tables_ready = true;
+}
+
+// Rows of M that carry conserved quantities: rho (sigma - P) and j (sigma u).
+inline bool conserved_row(int k) { return k == 0 || k == 3 || k == 5 || k == 7; }
+
+// ---------------------------------------------------------------------------
+// Parameters
+// ---------------------------------------------------------------------------
+struct Params {
+  int32_t nx, ny, nz;
+  int32_t bc[3];  // 0 periodic, 1 zero-gradient
+  double tau_f, tau_v, tau_e, tau_eps, tau_q;
+};
+
+// Diagonal of S (Eq. 31 generalised to D3Q19). tau_sigma = tau_j = dt for the
+// conserved rows (their deviation is set to zero, see collide_g). Reading: the
+// D3Q19 ghost rows (q, 3pi_xx, pi_ww, m) all relax with tau_q, and tau_q <= 0
+// means tau_q = tau_v (Case D of Sec. V.B sets tau_q = tau_v).
+template <class T>
+void rates(T tau_v, T tau_e, T tau_eps, T tau_q, T s[19]) {
+  for (int k = 0; k < 19; ++k) s[k] = T(0.0);
+  s[1] = T(1.0) / tau_e;
+  s[2] = T(1.0) / tau_eps;
+  s[4] = s[6] = s[8] = T(1.0) / tau_q;
+  s[9] = s[11] = s[13] = s[14] = s[15] = T(1.0) / tau_v;
+  s[10] = s[12] = T(1.0) / tau_q;
+  s[16] = s[17] = s[18] = T(1.0) / tau_q;
+}
+
+inline double real_part(double v) { return v; }
+inline double real_part(const cplx& v) { return v.real(); }
+
+// ---------------------------------------------------------------------------
+// Equilibria, Eqs. (7)-(9), with c_s^2 = 1/3 written out as in the paper.
+// ---------------------------------------------------------------------------
+template <class T>
+void f_equilibrium(T n_gamma, const T u[3], T feq[19]) {
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  for (int a = 0; a < 19; ++a) {
+    T eu = T(EV[a][0]) * u[0] + T(EV[a][1]) * u[1] + T(EV[a][2]) * u[2];
+    feq[a] = WV[a] * n_gamma *
+             (T(1.0) + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+// sigma = (eps + P) gamma^2.
+template <class T>
+void g_equilibrium(T sigma, T P, const T u[3], T geq[19]) {
+  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  geq[0] = WV[0] * sigma * (T(3.0) - P * (2.0 + 3.0 * CS2) / (sigma * CS2) - uu / (2.0 * CS2));
+  for (int a = 1; a < 19; ++a) {
+    T eu = T(EV[a][0]) * u[0] + T(EV[a][1]) * u[1] + T(EV[a][2]) * u[2];
+    geq[a] = WV[a] * sigma *
+             (P / (sigma * CS2) + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Recovery of the fields from the moments of Eq. (10). With P = eps/3 and
+// sigma = (eps + P) gamma^2 = 4 eps gamma^2 / 3, Eq. (10) reads
+//   E = sigma - P = sigma (3 + u^2)/4,   M = sigma u,
+// so |u| solves |M| u^2 - 4 E u + 3 |M| = 0. The subluminal root is
+//   |u| = (2E - sqrt(4E^2 - 3|M|^2)) / |M| = 3|M| / (2E + sqrt(4E^2 - 3|M|^2)),
+// and |u| < 1 exactly when |M| < E. A cell with E <= 0 or |M| >= E (or NaN)
+// has no admissible state; it is reported and left uncollided (a reading).
+// Squares are written as products so that complex-step derivatives stay exact.
+// ---------------------------------------------------------------------------
+template <class T>
+struct Fields {
+  T n, eps, P, gamma, u[3], sigma;
+};
+
+template <class T>
+bool recover(T N, T E, const T M[3], Fields<T>& F) {
+  T MM2 = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  double Er = real_part(E), M2r = real_part(MM2);
+  if (!(Er > 0.0) || !(M2r < Er * Er)) return false;
+  T q = T(3.0) / (T(2.0) * E + std::sqrt(T(4.0) * E * E - T(3.0) * MM2));
+  for (int i = 0; i < 3; ++i) F.u[i] = q * M[i];
+  T uu = F.u[0] * F.u[0] + F.u[1] * F.u[1] + F.u[2] * F.u[2];
+  F.sigma = T(4.0) * E / (T(3.0) + uu);
+  F.eps = T(0.75) * F.sigma * (T(1.0) - uu);
+  F.P = F.eps / T(3.0);
+  F.gamma = T(1.0) / std::sqrt(T(1.0) - uu);
+  F.n = N / F.gamma;
+  return true;
+}
+
+template <class T>
+void moments(const T f[19], const T g[19], T& N, T& E, T M[3]) {
+  N = T(0.0);
+  E = T(0.0);
+  M[0] = M[1] = M[2] = T(0.0);
+  for (int a = 0; a < 19; ++a) {
+    N += f[a];
+    E += g[a];
+    for (int i = 0; i < 3; ++i) M[i] += T(EV[a][i]) * g[a];
+  }
+}
+
+// g collision, Eqs. (30), (35): m = M g, m_eq = M g_eq,
+// m* = m - S (m - m_eq), g* = M^-1 m*. Reading: the conserved rows relax with
+// tau_sigma = tau_j = dt onto their own value, i.e. their (m - m_eq) is set to
+// zero (it differs from zero only by the rounding of the recovery).
+template <class T>
+void collide_g(const T g[19], const Fields<T>& F, const T s[19], T gout[19]) {
+  T geq[19], m[19], meq[19], ms[19];
+  g_equilibrium(F.sigma, F.P, F.u, geq);
+  for (int k = 0; k < 19; ++k) {
+    m[k] = T(0.0);
+    meq[k] = T(0.0);
+    for (int a = 0; a < 19; ++a) {
+      m[k] += MM[k][a] * g[a];
+      meq[k] += MM[k][a] * geq[a];
+    }
+    T d = conserved_row(k) ? T(0.0) : (m[k] - meq[k]);
+    ms[k] = m[k] - s[k] * d;
+  }
+  for (int a = 0; a < 19; ++a) {
+    gout[a] = T(0.0);
+    for (int k = 0; k < 19; ++k) gout[a] += MINV[a][k] * ms[k];
+  }
+}
+
+// f collision, Eq. (5): f* = f - (f - f_eq) / tau_f.
+template <class T>
+void collide_f(const T f[19], const Fields<T>& F, double tau_f, T fout[19]) {
+  T feq[19];
+  f_equilibrium(F.n * F.gamma, F.u, feq);
+  for (int a = 0; a < 19; ++a) fout[a] = f[a] - (f[a] - feq[a]) / tau_f;
+}
+
+// One cell of the g update from its pulled (pre-collision) populations.
+// Returns false (and copies) when the cell is inadmissible.
+template <class T>
+bool cell_g(const T g[19], const T s[19], T gout[19]) {
+  T E = T(0.0), M[3] = {T(0.0), T(0.0), T(0.0)};
+  for (int a = 0; a < 19; ++a) {
+    E += g[a];
+    for (int i = 0; i < 3; ++i) M[i] += T(EV[a][i]) * g[a];
+  }
+  Fields<T> F;
+  if (!recover(T(1.0), E, M, F)) {
+    for (int a = 0; a < 19; ++a) gout[a] = g[a];
+    return false;
+  }
+  collide_g(g, F, s, gout);
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Streaming source: the cell that e_a points away from, per axis wrapped
+// (periodic) or clamped (zero-gradient, the reading of "open" boundaries).
+// ---------------------------------------------------------------------------
+inline int src_coord(int c, int e, int N, int bc) {
+  int s = c - e;
+  if (bc == 0) {
+    s %= N;
+    if (s < 0) s += N;
+  } else {
+    if (s < 0) s = 0;
+    if (s > N - 1) s = N - 1;
+  }
+  return s;
+}
+
+inline int64_t src_cell(const Params& p, int x, int y, int z, int a) {
+  int sx = src_coord(x, EV[a][0], p.nx, p.bc[0]);
+  int sy = src_coord(y, EV[a][1], p.ny, p.bc[1]);
+  int sz = src_coord(z, EV[a][2], p.nz, p.bc[2]);
+  return ((int64_t)sz * p.ny + sy) * p.nx + sx;
+}
+
+double tau_q_of(const Params& p) { return p.tau_q > 0.0 ? p.tau_q : p.tau_v; }
+
+int g_threads = 0;
+
+}  // namespace
+
+// ===========================================================================
+// C entry points (ctypes). Populations are SoA: f[a * ncells + cell], the
+// cell index is x + nx (y + ny z).
+// ===========================================================================
+extern "C" {
+
+void oracle_set_threads(int n) {
+  g_threads = n;
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#endif
+}
+
+int oracle_max_threads() {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+void oracle_tables(int* e, double* w, double* M, double* Minv, double* norms) {
+  build_tables();
+  for (int a = 0; a < 19; ++a) {
+    for (int i = 0; i < 3; ++i) e[a * 3 + i] = EV[a][i];
+    w[a] = WV[a];
+  }
+  for (int k = 0; k < 19; ++k) {
+    norms[k] = NORM[k];
+    for (int a = 0; a < 19; ++a) {
+      M[k * 19 + a] = MM[k][a];
+      Minv[k * 19 + a] = MINV[k][a];
+    }
+  }
+}
+
+// D2Q9 lattice of Sec. V.A (Eqs. 31-34), used to check the moment basis
+// convention against the printed Eq. (34). Velocities: rest, (1,0), (0,1),
+// (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1); weights 4/9, 1/9, 1/36.
+// Basis rows: 1, 3r^2-4, (9r^4-21r^2+8)/2, x, (3r^2-5)x, y, (3r^2-5)y,
+// x^2-y^2, xy.
+void oracle_d2q9_tables(int* e, double* w, double* M) {
+  const int ev[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                        {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+  for (int a = 0; a < 9; ++a) {
+    double x = ev[a][0], y = ev[a][1], r2 = x * x + y * y;
+    e[2 * a] = ev[a][0];
+    e[2 * a + 1] = ev[a][1];
+    w[a] = (r2 == 0) ? 4.0 / 9.0 : (r2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+    double row[9] = {1.0, 3.0 * r2 - 4.0, (9.0 * r2 * r2 - 21.0 * r2 + 8.0) / 2.0, x,
+                     (3.0 * r2 - 5.0) * x, y, (3.0 * r2 - 5.0) * y, x * x - y * y, x * y};
+    for (int k = 0; k < 9; ++k) M[k * 9 + a] = row[k];
+  }
+}
+
+// D2Q9 g_eq, Eqs. (32)-(33).
+void oracle_d2q9_geq(double sigma, double P, const double* u, double* geq) {
+  int e[18];
+  double w[9], M[81];
+  oracle_d2q9_tables(e, w, M);
+  double uu = u[0] * u[0] + u[1] * u[1];
+  geq[0] = w[0] * sigma *
+           (9.0 / 4.0 - P * (5.0 + 9.0 * CS2) / (4.0 * sigma * CS2) - uu / (2.0 * CS2));
+  for (int a = 1; a < 9; ++a) {
+    double eu = e[2 * a] * u[0] + e[2 * a + 1] * u[1];
+    geq[a] = w[a] * sigma *
+             (P / (sigma * CS2) + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+void oracle_feq(double n, double gamma, const double* u, double* feq) {
+  build_tables();
+  f_equilibrium<double>(n * gamma, u, feq);
+}
+
+void oracle_geq(double eps, double P, const double* u, double* geq) {
+  build_tables();
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  double sigma = (eps + P) / (1.0 - uu);  // (eps + P) gamma^2
+  g_equilibrium<double>(sigma, P, u, geq);
+}
+
+// out = {n, eps, P, gamma, ux, uy, uz, sigma}; returns 1 if admissible.
+int oracle_recover(double N, double E, const double* M, double* out) {
+  Fields<double> F;
+  if (!recover<double>(N, E, M, F)) return 0;
+  out[0] = F.n;
+  out[1] = F.eps;
+  out[2] = F.P;
+  out[3] = F.gamma;
+  out[4] = F.u[0];
+  out[5] = F.u[1];
+  out[6] = F.u[2];
+  out[7] = F.sigma;
+  return 1;
+}
+
+void oracle_rates(const Params* p, double* s) {
+  rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), s);
+}
+
+// Collision of one cell (pre-collision f, g -> post-collision). Returns 1 if
+// the cell was admissible.
+int oracle_collide_cell(const Params* p, const double* f, const double* g, double* fout,
+                        double* gout) {
+  build_tables();
+  double N, E, M[3];
+  moments<double>(f, g, N, E, M);
+  Fields<double> F;
+  if (!recover<double>(N, E, M, F)) {
+    for (int a = 0; a < 19; ++a) {
+      fout[a] = f[a];
+      gout[a] = g[a];
+    }
+    return 0;
+  }
+  double s[19];
+  rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), s);
+  collide_f<double>(f, F, p->tau_f, fout);
+  collide_g<double>(g, F, s, gout);
+  return 1;
+}
+
+// State at t = 0: the equilibria of the initial fields (u has 3 planes),
+// f = f_eq(n0, u0), g = g_eq(eps0, P0 = eps0/3, u0).
+void oracle_init(const Params* p, const double* n0, const double* eps0, const double* u0,
+                 double* f, double* g) {
+  build_tables();
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+#pragma omp parallel for schedule(static)
+  for (int64_t c = 0; c < nc; ++c) {
+    double u[3] = {u0[c], u0[nc + c], u0[2 * nc + c]};
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    double gamma = 1.0 / std::sqrt(1.0 - uu);
+    double P = eps0[c] / 3.0;
+    double sigma = (eps0[c] + P) * gamma * gamma;
+    double fe[19], ge[19];
+    f_equilibrium<double>(n0[c] * gamma, u, fe);
+    g_equilibrium<double>(sigma, P, u, ge);
+    for (int a = 0; a < 19; ++a) {
+      f[a * nc + c] = fe[a];
+      g[a * nc + c] = ge[a];
+    }
+  }
+}
+
+// nsteps time steps in place. Each step: stream (pull), moments (Eq. 10),
+// recovery, equilibria (Eqs. 7-9), f BGK (Eq. 5), g MRT (Eq. 35).
+// Returns the number of inadmissible cell-updates.
+int64_t oracle_step(const Params* p, int32_t nsteps, double* f, double* g) {
+  build_tables();
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  double s[19];
+  rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), s);
+  std::vector<double> fn((size_t)(19 * nc)), gn((size_t)(19 * nc));
+  int64_t bad = 0;
+  for (int t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static) reduction(+ : bad) collapse(2)
+    for (int z = 0; z < p->nz; ++z)
+      for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+          int64_t c = ((int64_t)z * p->ny + y) * p->nx + x;
+          double fl[19], gl[19], fo[19], go[19];
+          for (int a = 0; a < 19; ++a) {
+            int64_t sc = src_cell(*p, x, y, z, a);
+            fl[a] = f[a * nc + sc];
+            gl[a] = g[a * nc + sc];
+          }
+          double N, E, M[3];
+          moments<double>(fl, gl, N, E, M);
+          Fields<double> F;
+          if (!recover<double>(N, E, M, F)) {
+            ++bad;
+            for (int a = 0; a < 19; ++a) {
+              fo[a] = fl[a];
+              go[a] = gl[a];
+            }
+          } else {
+            collide_f<double>(fl, F, p->tau_f, fo);
+            collide_g<double>(gl, F, s, go);
+          }
+          for (int a = 0; a < 19; ++a) {
+            fn[a * nc + c] = fo[a];
+            gn[a * nc + c] = go[a];
+          }
+        }
+    std::memcpy(f, fn.data(), sizeof(double) * 19 * nc);
+    std::memcpy(g, gn.data(), sizeof(double) * 19 * nc);
+  }
+  return bad;
+}
+
+// Fields of a stored state plus the lattice sums of n*gamma, sigma - P and
+// sigma*u (the T^{00}, T^{0i} integrals of Eqs. 2-3). Any output may be NULL.
+// sums = {sum N, sum E, sum Mx, sum My, sum Mz}. Returns the number of
+// inadmissible cells (their fields are NaN).
+int64_t oracle_fields(const Params* p, const double* f, const double* g, double* n, double* eps,
+                      double* P, double* gamma, double* u, double* sums) {
+  build_tables();
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  int64_t bad = 0;
+  double S0 = 0, S1 = 0, S2 = 0, S3 = 0, S4 = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    double fl[19], gl[19];
+    for (int a = 0; a < 19; ++a) {
+      fl[a] = f[a * nc + c];
+      gl[a] = g[a * nc + c];
+    }
+    double N, E, M[3];
+    moments<double>(fl, gl, N, E, M);
+    S0 += N;
+    S1 += E;
+    S2 += M[0];
+    S3 += M[1];
+    S4 += M[2];
+    Fields<double> F;
+    bool ok = recover<double>(N, E, M, F);
+    if (!ok) {
+      ++bad;
+      double q = std::nan("");
+      F.n = F.eps = F.P = F.gamma = F.u[0] = F.u[1] = F.u[2] = q;
+    }
+    if (n) n[c] = F.n;
+    if (eps) eps[c] = F.eps;
+    if (P) P[c] = F.P;
+    if (gamma) gamma[c] = F.gamma;
+    if (u) {
+      u[c] = F.u[0];
+      u[nc + c] = F.u[1];
+      u[2 * nc + c] = F.u[2];
+    }
+  }
+  if (sums) {
+    sums[0] = S0;
+    sums[1] = S1;
+    sums[2] = S2;
+    sums[3] = S3;
+    sums[4] = S4;
+  }
+  return bad;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of the g update (the loss involves only u and eps at the final time,
+// and g never reads f, so f drops out).
+//
+// Forward: g*(0) = g_eq(eps0, eps0/3, u0); for t = 0..T-1,
+//   g_pre(y) = g*(src(y, a), t), g*(y, t+1) = C(g_pre(y); tau).
+// Loss gradient: dL/du(T), dL/deps(T) given per cell, with (u, eps) the
+// recovery of g*(T).
+// Reverse: gbar*(T) = (d(u,eps)/dg)^T (dL/du, dL/deps);
+//   gbar_pre(y) = J_C(g_pre(y))^T gbar*(y, t+1),
+//   dL/dtau_k += gbar*(y, t+1) . dC/dtau_k,
+//   gbar*(x, t) = sum over (y, a) with src(y, a) = x of gbar_pre_a(y).
+// Init: dL/deps0, dL/du0 = (d g_eq / d(eps0, u0))^T gbar*(0).
+// Every Jacobian column is a complex-step derivative (h = 1e-30) of the same
+// templated per-cell code the forward oracle runs: exact to rounding.
+// tau is (tau_v, tau_e, tau_eps); tau_q follows tau_v when p->tau_q <= 0.
+// ---------------------------------------------------------------------------
+static const double CSH = 1e-30;
+
+static void cell_g_real(const double g[19], const double s[19], double out[19]) {
+  cell_g<double>(g, s, out);
+}
+
+static void rates_c(const Params& p, int which, cplx s[19]) {
+  cplx tv(p.tau_v), te(p.tau_e), tpe(p.tau_eps);
+  if (which == 0) tv += cplx(0.0, CSH);
+  if (which == 1) te += cplx(0.0, CSH);
+  if (which == 2) tpe += cplx(0.0, CSH);
+  cplx tq = p.tau_q > 0.0 ? cplx(p.tau_q) : tv;
+  rates<cplx>(tv, te, tpe, tq, s);
+}
+
+int oracle_grad(const Params* p, int32_t nsteps, const double* n0, const double* eps0,
+                const double* u0, const double* dL_du, const double* dL_deps, double* dL_dtau,
+                double* dL_deps0, double* dL_du0) {
+  build_tables();
+  (void)cell_g_real;
+  const int64_t nc = (int64_t)p->nx * p->ny * p->nz;
+  // Forward, storing g*(t) for t = 0..T.
+  std::vector<double> tape((size_t)(nsteps + 1) * 19 * nc);
+  std::vector<double> f((size_t)19 * nc);
+  oracle_init(p, n0, eps0, u0, f.data(), tape.data());
+  for (int t = 0; t < nsteps; ++t) {
+    std::memcpy(tape.data() + (size_t)(t + 1) * 19 * nc, tape.data() + (size_t)t * 19 * nc,
+                sizeof(double) * 19 * nc);
+    oracle_step(p, 1, f.data(), tape.data() + (size_t)(t + 1) * 19 * nc);
+  }
+  double sr[19];
+  rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), sr);
+  cplx sc[19];
+  for (int k = 0; k < 19; ++k) sc[k] = cplx(sr[k]);
+  cplx st[3][19];
+  for (int w = 0; w < 3; ++w) rates_c(*p, w, st[w]);
+
+  std::vector<double> gbar((size_t)19 * nc), gpre_bar((size_t)19 * nc);
+  // Loss at T.
+  const double* gT = tape.data() + (size_t)nsteps * 19 * nc;
+  for (int64_t c = 0; c < nc; ++c) {
+    for (int b = 0; b < 19; ++b) {
+      cplx E(0.0), M[3] = {cplx(0.0), cplx(0.0), cplx(0.0)};
+      for (int a = 0; a < 19; ++a) {
+        cplx ga(gT[a * nc + c], a == b ? CSH : 0.0);
+        E += ga;
+        for (int i = 0; i < 3; ++i) M[i] += double(EV[a][i]) * ga;
+      }
+      Fields<cplx> F;
+      double acc = 0.0;
+      if (recover<cplx>(cplx(1.0), E, M, F)) {
+        for (int i = 0; i < 3; ++i) acc += dL_du[i * nc + c] * F.u[i].imag() / CSH;
+        acc += dL_deps[c] * F.eps.imag() / CSH;
+      }
+      gbar[b * nc + c] = acc;
+    }
+  }
+  double dtau[3] = {0.0, 0.0, 0.0};
+  for (int t = nsteps - 1; t >= 0; --t) {
+    const double* gs = tape.data() + (size_t)t * 19 * nc;
+    double dt0 = 0.0, dt1 = 0.0, dt2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : dt0, dt1, dt2) collapse(2)
+    for (int z = 0; z < p->nz; ++z)
+      for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+          int64_t c = ((int64_t)z * p->ny + y) * p->nx + x;
+          double gl[19], ob[19];
+          for (int a = 0; a < 19; ++a) {
+            gl[a] = gs[a * nc + src_cell(*p, x, y, z, a)];
+            ob[a] = gbar[a * nc + c];
+          }
+          cplx gc[19], out[19];
+          for (int b = 0; b < 19; ++b) {
+            for (int a = 0; a < 19; ++a) gc[a] = cplx(gl[a], a == b ? CSH : 0.0);
+            cell_g<cplx>(gc, sc, out);
+            double acc = 0.0;
+            for (int a = 0; a < 19; ++a) acc += ob[a] * out[a].imag() / CSH;
+            gpre_bar[b * nc + c] = acc;
+          }
+          double dtl[3];
+          for (int w = 0; w < 3; ++w) {
+            for (int a = 0; a < 19; ++a) gc[a] = cplx(gl[a], 0.0);
+            cell_g<cplx>(gc, st[w], out);
+            double acc = 0.0;
+            for (int a = 0; a < 19; ++a) acc += ob[a] * out[a].imag() / CSH;
+            dtl[w] = acc;
+          }
+          dt0 += dtl[0];
+          dt1 += dtl[1];
+          dt2 += dtl[2];
+        }
+    dtau[0] += dt0;
+    dtau[1] += dt1;
+    dtau[2] += dt2;
+    // Transpose of the pull: scatter-add every pulled adjoint to its source.
+    std::fill(gbar.begin(), gbar.end(), 0.0);
+    for (int z = 0; z < p->nz; ++z)
+      for (int y = 0; y < p->ny; ++y)
+        for (int x = 0; x < p->nx; ++x) {
+          int64_t c = ((int64_t)z * p->ny + y) * p->nx + x;
+          for (int a = 0; a < 19; ++a) gbar[a * nc + src_cell(*p, x, y, z, a)] +=
+              gpre_bar[a * nc + c];
+        }
+  }
+  dL_dtau[0] = dtau[0];
+  dL_dtau[1] = dtau[1];
+  dL_dtau[2] = dtau[2];
+  // Init: g*(0) = g_eq(eps0, eps0/3, u0).
+  for (int64_t c = 0; c < nc; ++c) {
+    for (int w = 0; w < 4; ++w) {
+      cplx e0(eps0[c], w == 0 ? CSH : 0.0);
+      cplx u[3];
+      for (int i = 0; i < 3; ++i) u[i] = cplx(u0[i * nc + c], w == i + 1 ? CSH : 0.0);
+      cplx uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+      cplx P = e0 / 3.0;
+      cplx sigma = (e0 + P) / (cplx(1.0) - uu);
+      cplx ge[19];
+      g_equilibrium<cplx>(sigma, P, u, ge);
+      double acc = 0.0;
+      for (int a = 0; a < 19; ++a) acc += gbar[a * nc + c] * ge[a].imag() / CSH;
+      if (w == 0)
+        dL_deps0[c] = acc;
+      else
+        dL_du0[(w - 1) * nc + c] = acc;
+    }
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,159 @@
+"""Oracle pins: what the paper's analysis fixes for whole runs.
+
+* Stationarity of a uniform state (any u), periodic and zero-gradient.
+* Conservation of the lattice sums of n gamma, T^00 = sigma - P and
+  T^0i = sigma u_i under periodic boundaries (Eqs. 2-3).
+* Shear-wave decay with the viscosity set by tau_v:
+  eta = (tau_v - dt/2) c_s^2 sigma / gamma (text after Eq. 10 and after Eq. 36),
+  so a small shear wave decays at nu k^2 with nu = (tau_v - 1/2)/3.
+* Particle-number diffusion of Eq. (23): at u = 0 and uniform P the
+  particle number obeys a diffusion equation with phi = c_s^2 (tau_f - dt/2).
+* Bulk relaxation trend: a sound wave is damped more when tau_e grows (the
+  bulk viscosity after Eq. 36 grows with tau_e - dt/2).
+"""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (1, 1, 1), (0, 1, 0)])
+def test_uniform_state_is_stationary(orc, bc):
+    prob = wl.uniform(5, 4, 6, n=1.3, eps=2.1, u=(0.3, -0.2, 0.1), bc=bc,
+                      tau_f=0.7, tau_v=0.9, tau_e=0.6, tau_eps=1.1)
+    st = orc.State.init(prob)
+    f0, g0 = st.f.copy(), st.g.copy()
+    st.step(20)
+    assert np.abs(st.f - f0).max() < 1e-14 * np.abs(f0).max()
+    assert np.abs(st.g - g0).max() < 1e-14 * np.abs(g0).max()
+    F = st.fields()
+    assert np.abs(F["u"][0] - 0.3).max() < 1e-14
+    assert np.abs(F["n"] - 1.3).max() < 1e-14
+    assert np.abs(F["eps"] - 2.1).max() < 1e-13
+
+
+def test_periodic_conservation(orc):
+    prob = wl.random_modes(12, 10, 14, seed=5, umax=0.2, amp=0.1)
+    st = orc.State.init(prob)
+    s0 = st.fields()["sums"]
+    st.step(60)
+    s1 = st.fields()["sums"]
+    scale = np.abs(s0[:2]).max()
+    assert np.abs(s1 - s0).max() < 1e-13 * scale
+    assert st.bad == 0
+
+
+def _amplitude(field, k, axis_len):
+    y = np.arange(axis_len)
+    return 2.0 / axis_len * (field * np.sin(k * y)).sum()
+
+
+@pytest.mark.parametrize("tau_v,tau_e,tau_eps", [(0.8, 0.55, 0.7), (1.1, 1.1, 1.1),
+                                                 (0.6, 0.9, 0.6)])
+def test_shear_wave_decay(orc, tau_v, tau_e, tau_eps):
+    L = 128
+    k = 2 * np.pi / L
+    U = 1e-3
+    prob = wl.uniform(1, L, 1, n=1.0, eps=1.0, tau_f=0.8, tau_v=tau_v, tau_e=tau_e,
+                      tau_eps=tau_eps)
+    prob.u[0, 0, :, 0] = U * np.sin(k * np.arange(L))
+    st = orc.State.init(prob)
+    t0, t1 = 200, 1800
+    st.step(t0)
+    a0 = _amplitude(st.fields()["u"][0, 0, :, 0], k, L)
+    st.step(t1 - t0)
+    a1 = _amplitude(st.fields()["u"][0, 0, :, 0], k, L)
+    rate = -np.log(a1 / a0) / (t1 - t0)
+    nu = (tau_v - 0.5) / 3.0
+    assert abs(rate / (nu * k * k) - 1.0) < 0.01
+
+
+@pytest.mark.parametrize("tau_f", [0.6, 0.9, 1.4])
+def test_particle_number_diffusion(orc, tau_f):
+    L = 64
+    k = 2 * np.pi / L
+    prob = wl.uniform(1, 1, L, n=1.0, eps=1.0, tau_f=tau_f, tau_v=0.8, tau_e=0.55,
+                      tau_eps=0.7)
+    z = np.arange(L)
+    prob.n[:, 0, 0] = 1.0 + 1e-3 * np.sin(k * z)
+    st = orc.State.init(prob)
+    t0, t1 = 50, 450
+    st.step(t0)
+    a0 = _amplitude(st.fields()["n"][:, 0, 0] - 1.0, k, L)
+    st.step(t1 - t0)
+    a1 = _amplitude(st.fields()["n"][:, 0, 0] - 1.0, k, L)
+    rate = -np.log(a1 / a0) / (t1 - t0)
+    phi = (tau_f - 0.5) / 3.0
+    assert abs(rate / (phi * k * k) - 1.0) < 0.01
+    # g never reads f: the flow stays at rest (to rounding of M^-1)
+    assert np.abs(st.fields()["u"]).max() < 1e-13
+
+
+def test_particle_number_depends_on_tau_f_only_through_f(orc):
+    """Eq. (23): the shock-tube particle number depends on tau_f while the
+    energy-momentum fields do not (g never reads f)."""
+    outs = {}
+    for tf in (0.55, 0.9):
+        prob = wl.shock_tube(200, tau=0.9, tau_f=tf)
+        st = orc.run(prob, 100)
+        outs[tf] = st.fields()
+    a, b = outs[0.55], outs[0.9]
+    assert np.array_equal(a["eps"], b["eps"]) and np.array_equal(a["u"], b["u"])
+    assert np.abs(a["n"] - b["n"]).max() > 1e-3
+    # larger tau_f -> more diffusion -> smoother (smaller total variation)
+    tv = lambda x: np.abs(np.diff(x.ravel())).sum()
+    assert tv(b["n"]) < tv(a["n"])
+
+
+def test_bulk_relaxation_damps_sound(orc):
+    L = 64
+    k = 2 * np.pi / L
+    amps = []
+    for tau_e in (0.52, 0.8, 1.2):
+        prob = wl.uniform(1, 1, L, n=1.0, eps=1.0, tau_f=0.8, tau_v=0.8, tau_e=tau_e,
+                          tau_eps=0.8)
+        prob.eps[:, 0, 0] = 1.0 + 1e-3 * np.sin(k * np.arange(L))
+        st = orc.State.init(prob)
+        st.step(300)
+        F = st.fields()
+        # acoustic energy: pressure and momentum fluctuations
+        amps.append(np.abs(F["eps"] - F["eps"].mean()).max() + np.abs(F["u"][2]).max())
+    assert amps[0] > amps[1] > amps[2]
+
+
+def test_particle_bump_is_carried_by_the_flow(orc):
+    """Eq. (23) convection: a particle-number bump in a uniform flow u_z moves
+    downstream at u_z (pins the direction of streaming, Eqs. 5-6)."""
+    L = 128
+    uz = 0.1
+    prob = wl.uniform(1, 1, L, n=1.0, eps=1.0, u=(0.0, 0.0, uz), tau_f=0.52, tau_v=0.8,
+                      tau_e=0.8, tau_eps=0.8)
+    z = np.arange(L)
+    prob.n[:, 0, 0] = 1.0 + 1e-3 * np.exp(-((z - 40.0) / 4.0) ** 2)
+    st = orc.State.init(prob)
+
+    def centroid():
+        d = st.fields()["n"][:, 0, 0] - 1.0
+        return (d * z).sum() / d.sum()
+
+    c0 = centroid()
+    st.step(200)
+    assert abs((centroid() - c0) - uz * 200) < 0.5
+
+
+def test_open_ends_keep_far_field(orc):
+    """Zero-gradient ("open") ends leave a uniform end region untouched until
+    the shock waves arrive; a periodic tube instead starts a second Riemann
+    problem where the two ends meet."""
+    L = 200
+    res = {}
+    for bc in (1, 0):
+        prob = wl.shock_tube(L, tau=0.9)
+        prob.params.bc = (0, 0, bc)
+        st = orc.run(prob, 40)
+        res[bc] = st.fields()["eps"][:, 0, 0]
+    eps0 = wl.shock_tube(L)
+    assert np.abs(res[1][:20] - eps0.eps[:20, 0, 0]).max() < 1e-12
+    assert np.abs(res[1][-20:] - eps0.eps[-20:, 0, 0]).max() < 1e-12
+    assert np.abs(res[0][:20] - eps0.eps[:20, 0, 0]).max() > 1e-3

@@ -1,0 +1,318 @@
+"""Seeded synthetic inputs shaped like the paper's relativistic flow problems.
+
+This module is shared by the GPU path and the FP64 oracle: it only draws and
+lays out initial fields and relaxation times. It holds none of the lattice
+Boltzmann arithmetic (no equilibria, moments, recovery or collision).
+
+Conventions
+-----------
+* A lattice of ``nx * ny * nz`` cells is stored C-ordered as ``(nz, ny, nx)``
+  (x fastest). Vector fields are ``(3, nz, ny, nx)``.
+* Every field is float64. The pressure values the problems are stated in are
+  turned into energy density with the ideal ultra-relativistic equation of
+  state the method runs with, P = eps / 3, so ``eps = 3 * P``.
+* Boundary kinds: 0 = periodic, 1 = zero-gradient ("open").
+
+Problems (the paper publishes no data set; these stand in for its
+quark-gluon-plasma shock tubes of Sec. III.B and Sec. V.B and for the blast
+problem class the model was built for):
+
+``shock_tube``     quasi-1D Riemann problem on 1 x 1 x L cells (Sec. III.B).
+``random_modes``   3D periodic smooth random flow (16 Fourier modes).
+``tube_batch``     64 ragged shock tubes with per-tube relaxation times.
+``shear_vortex``   2D periodic shear wave + Taylor-Green vortex (adjoint).
+``blast``          3D spherical blast with an outward velocity shell.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+PERIODIC = 0
+ZERO_GRADIENT = 1
+
+
+@dataclasses.dataclass
+class Params:
+    """Lattice size, boundary kinds and relaxation times of one lattice."""
+
+    nx: int
+    ny: int
+    nz: int
+    bc: Tuple[int, int, int] = (PERIODIC, PERIODIC, PERIODIC)
+    tau_f: float = 0.9
+    tau_v: float = 0.9
+    tau_e: float = 0.9
+    tau_eps: float = 0.9
+    tau_q: float = 0.0  # <= 0: ghost moments relax with tau_v
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+@dataclasses.dataclass
+class Problem:
+    """Initial fields (float64) plus the lattice parameters."""
+
+    params: Params
+    n: np.ndarray
+    eps: np.ndarray
+    u: np.ndarray
+    name: str = ""
+    meta: Dict = dataclasses.field(default_factory=dict)
+
+
+def _tanh_step(i: np.ndarray, center: float, width: float, left: float, right: float) -> np.ndarray:
+    """left for i << center, right for i >> center, smoothed over ~2 cells."""
+    s = 0.5 * (1.0 - np.tanh((i + 0.5 - center) / width))
+    return right + (left - right) * s
+
+
+def shock_tube(length: int = 800, P_L: float = 1.0, n_L: float = 1.0, P_R: float = 0.41,
+               n_R: float = 0.55, width: float = 1.0, tau: float = 0.9,
+               tau_f: float | None = None) -> Problem:
+    """Quasi-1D Riemann problem at rest on a 1 x 1 x ``length`` lattice.
+
+    The long axis is z with zero-gradient ends; the two transverse axes have
+    one cell and are periodic. The jump sits between cells length/2 - 1 and
+    length/2 and is smoothed with a tanh of width ``width`` cells.
+    """
+    z = np.arange(length, dtype=np.float64)
+    P = _tanh_step(z, length / 2.0, width, P_L, P_R)
+    n = _tanh_step(z, length / 2.0, width, n_L, n_R)
+    shape = (length, 1, 1)
+    prm = Params(1, 1, length, (PERIODIC, PERIODIC, ZERO_GRADIENT), tau_f if tau_f else tau,
+                 tau, tau, tau)
+    return Problem(prm, n.reshape(shape).copy(), (3.0 * P).reshape(shape).copy(),
+                   np.zeros((3,) + shape), name=f"shock_tube_1x1x{length}")
+
+
+def _mode_set(rng: np.random.Generator, n_modes: int, kmax: float, ndim: int):
+    """Draw ``n_modes`` integer wave vectors with 1 <= |k| <= kmax."""
+    ks = []
+    r = int(math.floor(kmax))
+    while len(ks) < n_modes:
+        k = rng.integers(-r, r + 1, size=3)
+        if ndim == 2:
+            k[2] = 0
+        kk = float(np.sqrt((k * k).sum()))
+        if 1.0 <= kk <= kmax:
+            ks.append(k)
+    return np.array(ks, dtype=np.int64)
+
+
+def _mode_sum(shape, ks, amps, phases):
+    """sum_m amps[m] * cos(2 pi k_m . x / L + phase_m) on the (nz, ny, nx) grid.
+
+    ``amps`` is (n_modes, ncomp). Returns (ncomp, nz, ny, nx). Evaluated as a
+    product of 1D complex exponentials per axis.
+    """
+    nz, ny, nx = shape
+    ncomp = amps.shape[1]
+    out = np.zeros((ncomp,) + shape)
+    x = np.arange(nx)
+    y = np.arange(ny)
+    z = np.arange(nz)
+    for m in range(ks.shape[0]):
+        kx, ky, kz = ks[m]
+        ax = np.exp(2j * np.pi * ((kx * x) % nx) / nx)
+        ay = np.exp(2j * np.pi * ((ky * y) % ny) / ny)
+        az = np.exp(1j * (2 * np.pi * ((kz * z) % nz) / nz + phases[m]))
+        plane = ay[:, None] * ax[None, :]
+        wave = (az[:, None, None] * plane[None, :, :]).real
+        for c in range(ncomp):
+            out[c] += amps[m, c] * wave
+    return out
+
+
+def _noise(rng, shape, n_modes=16, kmax=4.0, ndim=3):
+    ks = _mode_set(rng, n_modes, kmax, ndim)
+    amps = rng.standard_normal((n_modes, 1))
+    ph = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    f = _mode_sum(shape, ks, amps, ph)[0]
+    return f / np.abs(f).max()
+
+
+def random_modes(nx: int = 256, ny: int | None = None, nz: int | None = None, seed: int = 1211,
+                 umax: float = 0.1, amp: float = 0.05, n_modes: int = 16, kmax: float = 4.0,
+                 tau_v: float = 0.8, tau_e: float = 0.55, tau_eps: float = 0.7,
+                 tau_f: float = 0.8, bc=(PERIODIC, PERIODIC, PERIODIC)) -> Problem:
+    """Smooth periodic random flow: 16 modes with integer |k| <= 4.
+
+    u = sum of vector-amplitude cosine modes scaled to max|u| = umax;
+    eps = 1 + amp * noise, n = 1 + amp * noise' with noise fields built the
+    same way and normalised to max|noise| = 1.
+    """
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    shape = (nz, ny, nx)
+    ndim = 2 if nz == 1 else 3
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ks = _mode_set(rng, n_modes, kmax, ndim)
+    amps = rng.standard_normal((n_modes, 3))
+    if ndim == 2:
+        amps[:, 2] = 0.0
+    ph = rng.uniform(0.0, 2.0 * np.pi, n_modes)
+    u = _mode_sum(shape, ks, amps, ph)
+    speed = np.sqrt((u * u).sum(axis=0)).max()
+    u *= umax / speed
+    eps = 1.0 + amp * _noise(rng, shape, n_modes, kmax, ndim)
+    n = 1.0 + amp * _noise(rng, shape, n_modes, kmax, ndim)
+    prm = Params(nx, ny, nz, tuple(bc), tau_f, tau_v, tau_e, tau_eps)
+    return Problem(prm, n, eps, u, name=f"random_modes_{nx}x{ny}x{nz}_seed{seed}")
+
+
+def tube_batch(n_tubes: int = 64, seed: int = 3286, lmin: int = 400, lmax: int = 3200,
+               ratio: Tuple[float, float] = (1.5, 5.0), tau_v: Tuple[float, float] = (0.6, 2.0),
+               a: Tuple[float, float] = (0.05, 1.0), tau_eps: Tuple[float, float] = (0.6, 1.5),
+               width: float = 1.0) -> List[Problem]:
+    """Ragged batch of quasi-1D shock tubes (high-viscosity regime).
+
+    Per tube: L ~ U{lmin..lmax}; P_L = 1, P_R = 1/r with r ~ U(ratio);
+    n = P^(3/4); u = 0; tau_v ~ U(tau_v); tau_e = 1/2 + a (tau_v - 1/2) with
+    a ~ U(a) (the paper's bulk/shear relaxation parameterisation of Cases C/D);
+    tau_eps ~ U(tau_eps); tau_f = tau_v.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(n_tubes):
+        L = int(rng.integers(lmin, lmax + 1))
+        r = float(rng.uniform(*ratio))
+        tv = float(rng.uniform(*tau_v))
+        aa = float(rng.uniform(*a))
+        te = 0.5 + aa * (tv - 0.5)
+        tpe = float(rng.uniform(*tau_eps))
+        z = np.arange(L, dtype=np.float64)
+        P = _tanh_step(z, L / 2.0, width, 1.0, 1.0 / r)
+        n = P ** 0.75
+        shape = (L, 1, 1)
+        prm = Params(1, 1, L, (PERIODIC, PERIODIC, ZERO_GRADIENT), tv, tv, te, tpe)
+        out.append(Problem(prm, n.reshape(shape).copy(), (3.0 * P).reshape(shape).copy(),
+                           np.zeros((3,) + shape), name=f"tube{b}_L{L}",
+                           meta={"ratio": r, "a": aa}))
+    return out
+
+
+def shear_vortex(L: int = 512, seed: int = 1212, umax: float = 0.1, amp: float = 0.05,
+                 tau_v: float = 0.8, tau_e: float = 0.55, tau_eps: float = 0.7,
+                 tau_f: float = 0.8) -> Problem:
+    """2D periodic L x L x 1 field: shear wave plus a Taylor-Green vortex.
+
+    u_x = U0 sin(2 pi y / L) + sin(kx) cos(ky), u_y = -cos(kx) sin(ky) with
+    k = 2 pi / L, scaled to max|u| = umax; eps = 1 + amp * noise; n = 1.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (1, L, L)
+    k = 2.0 * np.pi / L
+    x = np.arange(L)[None, None, :]
+    y = np.arange(L)[None, :, None]
+    u = np.zeros((3,) + shape)
+    u[0] = 1.0 * np.sin(k * y) + np.sin(k * x) * np.cos(k * y)
+    u[1] = -np.cos(k * x) * np.sin(k * y) + 0.0 * x
+    u *= umax / np.sqrt((u * u).sum(axis=0)).max()
+    eps = 1.0 + amp * _noise(rng, shape, ndim=2)
+    n = np.ones(shape)
+    prm = Params(L, L, 1, (PERIODIC, PERIODIC, PERIODIC), tau_f, tau_v, tau_e, tau_eps)
+    return Problem(prm, n, eps, u, name=f"shear_vortex_{L}x{L}")
+
+
+def perturbed_taus(base: Tuple[float, float, float], seed: int = 1212, rel: float = 0.05):
+    """Target relaxation times tau'_k = tau_k + rel (tau_k - 1/2) z_k, z ~ N(0, 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    z = rng.standard_normal(3)
+    return tuple(float(t + rel * (t - 0.5) * zz) for t, zz in zip(base, z))
+
+
+def target_noise(shape, seed: int = 1212, rel: float = 0.01):
+    """Per-cell standard normal draws for the 1 % target noise: (4, *shape)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 11))
+    return rng.standard_normal((4,) + tuple(shape))
+
+
+def blast(L: int = 512, radius: float | None = None, shell: float | None = None,
+          seed: int = 1213, P_in: float = 10.0, P_out: float = 0.1, umax: float = 0.6,
+          tau_v: float = 0.9, tau_e: float = 0.62, tau_eps: float = 0.8,
+          tau_f: float | None = None, width: float = 1.0) -> Problem:
+    """Moderately relativistic 3D blast on an L^3 lattice with zero-gradient faces.
+
+    P = P_in inside a sphere of radius L/8 (64 at L = 512), P_out outside
+    (tanh width 1); n = P^(3/4); outward velocity shell
+    u = umax exp(-((r - R)/w)^2)(1 + 0.1 noise) r_hat, w = R/8, rescaled to
+    max|u| = umax.
+    """
+    R = L / 8.0 if radius is None else radius
+    w = R / 8.0 if shell is None else shell
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (L, L, L)
+    c = (L - 1) / 2.0
+    ax = np.arange(L, dtype=np.float64) - c
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    r = np.sqrt(X * X + Y * Y + Z * Z)
+    P = P_out + (P_in - P_out) * 0.5 * (1.0 - np.tanh((r - R) / width))
+    n = P ** 0.75
+    noise = _noise(rng, shape)
+    mag = np.exp(-((r - R) / w) ** 2) * (1.0 + 0.1 * noise)
+    rs = np.where(r > 0, r, 1.0)
+    u = np.stack([mag * X / rs, mag * Y / rs, mag * Z / rs])
+    u *= umax / np.sqrt((u * u).sum(axis=0)).max()
+    tf = tau_v if tau_f is None else tau_f
+    prm = Params(L, L, L, (ZERO_GRADIENT,) * 3, tf, tau_v, tau_e, tau_eps)
+    return Problem(prm, n, 3.0 * P, u, name=f"blast_{L}^3")
+
+
+def uniform(nx: int, ny: int, nz: int, n: float = 1.0, eps: float = 1.0,
+            u=(0.0, 0.0, 0.0), **tau) -> Problem:
+    """A uniform state (every cell identical)."""
+    shape = (nz, ny, nx)
+    uu = np.empty((3,) + shape)
+    for c in range(3):
+        uu[c] = u[c]
+    prm = Params(nx, ny, nz, tau.pop("bc", (PERIODIC,) * 3), **tau)
+    return Problem(prm, np.full(shape, n), np.full(shape, eps), uu, name="uniform")
+
+
+def window(problem: Problem, center: Tuple[int, int, int], half: int):
+    """Cut the neighbourhood of ``center`` (z, y, x) that decides it after ``half`` steps.
+
+    Returns (sub_problem, local_center). Periodic axes wrap (an axis shorter
+    than 2*half+1 is taken whole); zero-gradient axes are cut at the real
+    boundary, where the sub-lattice keeps the zero-gradient rule.
+    """
+    prm = problem.params
+    dims = (prm.nz, prm.ny, prm.nx)
+    bcs = (prm.bc[2], prm.bc[1], prm.bc[0])
+    idx = []
+    loc = []
+    sub_bc = []
+    for a in range(3):
+        N = dims[a]
+        c = center[a]
+        if 2 * half + 1 >= N:
+            idx.append(np.arange(N))
+            loc.append(c)
+            sub_bc.append(bcs[a])
+        elif bcs[a] == PERIODIC:
+            idx.append((c + np.arange(-half, half + 1)) % N)
+            loc.append(half)
+            sub_bc.append(ZERO_GRADIENT)
+        else:
+            lo = max(0, c - half)
+            hi = min(N - 1, c + half)
+            idx.append(np.arange(lo, hi + 1))
+            loc.append(c - lo)
+            sub_bc.append(ZERO_GRADIENT)
+    iz, iy, ix = np.ix_(*idx)
+    sub = Params(len(idx[2]), len(idx[1]), len(idx[0]), (sub_bc[2], sub_bc[1], sub_bc[0]),
+                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q)
+    u = np.stack([problem.u[c][iz, iy, ix] for c in range(3)])
+    return (Problem(sub, problem.n[iz, iy, ix].copy(), problem.eps[iz, iy, ix].copy(), u,
+                    name=problem.name + "_window"), tuple(loc))
