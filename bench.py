@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the relativistic MRT lattice Boltzmann step on one MI355X.
+
+Headline workload: a 256^3 periodic lattice (D3Q19, two distributions), smooth
+random flow from 16 Fourier modes (|k| <= 4, max|u| = 0.1, eps and n = 1 +
+0.05 noise, seed 1211), tau_v = 0.8, tau_e = 0.55, tau_eps = 0.7, tau_f = 0.8,
+FP32 populations with FP64 recovery and FP64 conservation sums fused into
+every step. One timed step = one fused kernel launch over all 16.8M cells.
+
+Also reported ("forms"): the same step in FP64, the batched persistent
+launch over 64 ragged shock tubes (3000 steps, one graph launch), and the
+adjoint gradient of a 512 x 512 run (1000 steps, checkpoints every 50).
+
+Prints one JSON line. ``value`` is MLUPS (million lattice-cell updates per
+second) with the populations resident in HBM; ``roofline`` prices the fused
+kernel at its algorithmic traffic (2 x 38 populations per cell update);
+``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same
+workload on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % HBM roofline, FP32 vs FP64 step, batched and adjoint, at stated error"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1211_3286_amd", "csrc", f)
+                  for f in ("cell.hpp", "kernels.hip")]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, cells: int):
+    """HBM bytes per launch from the committed PMC summary, if it still
+    describes the current kernel source (else None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        db = json.load(fh)
+    rec = db.get(kernel)
+    if not rec or rec.get("source_hash") != kernel_hash() or rec.get("cells") != cells:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_steps(torch, sim, steps: int, warmup: int):
+    if warmup:
+        sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def copy_calibration(torch, nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device-to-device copy of known size: its byte counters give the
+    scale of the FETCH_SIZE / WRITE_SIZE counters of the step kernel."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms,
+            "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def bench_lattice(torch, rlb, wl, n: int, precision: int, steps: int, warmup: int,
+                  diag_every: int):
+    prob = wl.random_modes(n, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    sim = rlb.from_problems(prob, precision=precision, diag_every=diag_every)
+    tune = sim.tune(trial_steps=3)
+    log("tuned", tune["name"], {k: round(v, 4) for k, v in tune["ms_per_step"].items()})
+    s0 = sim.sums()
+    ms, wall = time_steps(torch, sim, steps, warmup)
+    s1 = sim.sums()
+    diag, dstep, bad = sim.diagnostics()
+    cells = prob.params.ncells
+    bytes_per_cell = 2 * 38 * (4 if precision == rlb.FP32 else 8)
+    drift = float(abs(s1 - s0).max() / abs(s0[:2]).max())
+    out = {"ms_per_step": ms, "mlups": cells / (ms * 1e-3) / 1e6, "cells": cells,
+           "kernel": sim.kernel_name, "bytes_per_cell": bytes_per_cell,
+           "achieved_gbs": bytes_per_cell * cells / (ms * 1e-3) / 1e9,
+           "conservation_drift": drift, "inadmissible": bad, "wall_s": wall,
+           "variant_ms": tune["ms_per_step"], "problem": prob}
+    out["frac"] = out["achieved_gbs"] / HBM_PEAK_GBS
+    sim.close()
+    return out
+
+
+def bench_batched(torch, rlb, wl, steps: int = 3000):
+    tubes = wl.tube_batch()
+    sim = rlb.from_problems(tubes, precision=rlb.FP32)
+    tune = sim.tune(trial_steps=50)
+    log("batched tuned", tune["name"], {k: round(v, 5) for k, v in tune["ms_per_step"].items()})
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = sum(t.params.ncells for t in tubes)
+    m = sim.moments(allow_unphysical=True)
+    res = {"tubes": len(tubes), "steps": steps, "cells": cells, "ms_total": ms,
+           "tube_steps_per_s": len(tubes) * steps / (ms * 1e-3),
+           "mlups": cells * steps / (ms * 1e-3) / 1e6,
+           "effective_gbs": 304 * cells * steps / (ms * 1e-3) / 1e9,
+           "kernel": sim.kernel_name, "launches": 1, "graph": True, "inadmissible": m["bad"],
+           "note": "working set ~35 MB stays in L2/MALL; effective GB/s is not HBM traffic"}
+    sim.close()
+    return res
+
+
+def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50):
+    import numpy as np
+    prob = wl.shear_vortex(L)
+    p = prob.params
+    try:
+        sim = rlb.from_problems(prob, precision=rlb.FP32, ckpt_every=K, tape_steps=steps)
+    except rlb.RLBError as e:
+        return {"status": str(e)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    m = sim.moments()
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    du = torch.randn(3, sim.ncells, dtype=torch.float64, device=sim.device) * 1e-2
+    de = torch.randn(sim.ncells, dtype=torch.float64, device=sim.device) * 1e-2
+    t0 = time.perf_counter()
+    try:
+        dtau, de0, du0 = sim.grad(du, de)
+    except rlb.RLBError as e:
+        return {"status": str(e), "forward_s": t_fwd}
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    cells = sim.ncells
+    return {"lattice": f"{L}x{L}x1", "steps": steps, "ckpt_every": K, "forward_s": t_fwd,
+            "gradient_s": t_bwd, "cell_steps_per_s": cells * steps / (t_fwd + t_bwd),
+            "bytes_per_cell_step": 684,
+            "effective_gbs": 684 * cells * steps / (t_fwd + t_bwd) / 1e9,
+            "dL_dtau": [float(x) for x in dtau]}
+
+
+def cpu_baseline(prob, seconds: float):
+    """The FP64 oracle on the host cores, on whole steps of the same lattice."""
+    import oracle
+    threads = oracle.max_threads()
+    st = oracle.State.init(prob)
+    t0 = time.perf_counter()
+    st.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, int(seconds / max(one, 1e-9)) - 1)
+    t0 = time.perf_counter()
+    st.step(n)
+    dt = time.perf_counter() - t0
+    cells = prob.params.ncells
+    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n} FP64 steps of the full {prob.params.nx}x{prob.params.ny}x"
+                      f"{prob.params.nz} lattice (after 1 untimed step), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="only the headline FP32 step")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--diag-every", type=int, default=50,
+                    help="fuse the FP64 conservation sums into every N-th step")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1211_3286_amd as rlb
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    prec = rlb.FP32 if args.precision == "fp32" else rlb.FP64
+    log(f"lattice {args.size}^3 {args.precision}: warmup {args.warmup}, steps {args.steps}")
+    head = bench_lattice(torch, rlb, wl, args.size, prec, args.steps, args.warmup,
+                         args.diag_every)
+    log("headline", {k: v for k, v in head.items() if k not in ("problem", "variant_ms")})
+    traffic = measured_traffic(head["kernel"], head["cells"])
+    roof = {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["frac"], 4), "traffic": traffic,
+            "kernel": head["kernel"], "algorithmic_bytes_per_launch":
+                head["bytes_per_cell"] * head["cells"]}
+    forms = {}
+    if not args.no_forms:
+        other = rlb.FP64 if prec == rlb.FP32 else rlb.FP32
+        o = bench_lattice(torch, rlb, wl, args.size, other, max(args.steps // 2, 10),
+                          max(args.warmup // 2, 2), args.diag_every)
+        forms["fp64" if other == rlb.FP64 else "fp32"] = {
+            k: o[k] for k in ("mlups", "ms_per_step", "achieved_gbs", "frac", "kernel",
+                              "conservation_drift")}
+        log("other precision", forms)
+        forms["batched"] = bench_batched(torch, rlb, wl)
+        log("batched", forms["batched"])
+        forms["adjoint"] = bench_adjoint(torch, rlb, wl)
+        log("adjoint", forms["adjoint"])
+    if args.copy_calibration:
+        forms["copy_calibration"] = copy_calibration(torch)
+        log("copy", forms["copy_calibration"])
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(head["problem"], args.cpu_seconds)
+        log("cpu", cpu)
+    p = head["problem"].params
+    line = {
+        "metric": METRIC, "value": round(head["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == rlb.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"random_modes_{p.nx}x{p.ny}x{p.nz}_periodic_seed1211",
+                   "lattice": "D3Q19 f+g", "cells": head["cells"], "tau_v": p.tau_v,
+                   "tau_e": p.tau_e, "tau_eps": p.tau_eps, "tau_f": p.tau_f,
+                   "recovery": "fp64", "diag_every": args.diag_every},
+        "roofline": roof, "cpu_baseline": cpu,
+        "conservation_drift": head["conservation_drift"], "inadmissible": head["inadmissible"],
+        "forms": forms,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * rlb.h - C ABI of the MI355X (gfx950) relativistic lattice Boltzmann step.
+ *
+ * Model: Q. Li, K. H. Luo, X. J. Li, "Lattice Boltzmann method for relativistic
+ * hydrodynamics: issues on conservation law of particle number and
+ * discontinuities" (arXiv:1211.3286), Sec. II and Sec. V.A. Two distributions
+ * per cell on the D3Q19 lattice:
+ *   f  particle number,   BGK collision with tau_f      (Eq. 5, f_eq Eq. 7)
+ *   g  energy-momentum,   MRT collision, Lambda = M^-1 S M (Eqs. 30, 31, 35;
+ *                         g_eq Eqs. 8-9), relaxation times tau_v (shear rows),
+ *                         tau_e (energy/bulk row), tau_eps (energy-square row),
+ *                         tau_q (ghost rows); tau_sigma = tau_j = dt.
+ * Macroscopic fields (Eq. 10): n gamma = sum f, (eps + P) gamma^2 - P = sum g,
+ * (eps + P) gamma^2 u = sum e g, with the equation of state P = eps / 3.
+ * The recovery of (n, eps, P, gamma, u) from these sums, the conservation sums
+ * and every reduction are done in FP64 whatever the population precision.
+ *
+ * Lattice units: dt = dx = c = 1, c_s^2 = 1/3.
+ *
+ * Velocity order (index a of every population array):
+ *   0: (0,0,0)
+ *   1: (+1,0,0)  2: (-1,0,0)  3: (0,+1,0)  4: (0,-1,0)  5: (0,0,+1)  6: (0,0,-1)
+ *   7: (+1,+1,0) 8: (-1,-1,0) 9: (+1,-1,0) 10: (-1,+1,0)
+ *  11: (+1,0,+1) 12: (-1,0,-1) 13: (+1,0,-1) 14: (-1,0,+1)
+ *  15: (0,+1,+1) 16: (0,-1,-1) 17: (0,+1,-1) 18: (0,-1,+1)
+ *
+ * Field layout: a lattice of nx*ny*nz cells, x fastest: cell = x + nx*(y + ny*z).
+ * A batch of members ("n_members" lattices, e.g. shock tubes of uneven
+ * length) is packed member after member; member m starts at the prefix sum of
+ * the cell counts of members 0..m-1. Scalar fields are arrays of that many
+ * doubles; a velocity field is three such planes (u_x, u_y, u_z).
+ *
+ * Time: the state after step t holds the post-collision populations at t;
+ * rlb_init sets the state at t = 0 to the equilibria of the given fields.
+ * One rlb_step advances every cell by: streaming (pull from x - e_a, with
+ * periodic wrap or zero-gradient clamp per axis), the Eq. (10) sums, the
+ * recovery, the equilibria, the f BGK and g MRT collisions.
+ *
+ * Ownership: the caller owns every buffer. The library never allocates device
+ * memory: all device state lives in the caller's workspace, whose size
+ * rlb_workspace_size reports, and which must stay valid (and untouched by the
+ * caller) until rlb_free. All device work is enqueued on the caller's HIP
+ * stream given to rlb_init (NULL = the null stream); calls that return host
+ * data synchronise that stream. Pointers marked "device" must be device
+ * memory of the device that was current at rlb_init; "host" pointers are
+ * ordinary host memory. A handle must not be used from two threads at once.
+ *
+ * Errors: every call returns an rlb_status; nothing is thrown and nothing
+ * exits. A failed call leaves the state as it was unless stated otherwise.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RLB_OK = 0,
+  RLB_E_ARG = -1,         /* NULL pointer, bad size, bad enum, bad dims */
+  RLB_E_TAU = -2,         /* a relaxation time <= 1/2 (negative viscosity) or not finite */
+  RLB_E_UNPHYSICAL = -3,  /* an input cell has eps <= 0, n < 0 or |u| >= 1; or cells
+                             became inadmissible (E <= 0 or |M| >= E) during steps */
+  RLB_E_WORKSPACE = -4,   /* workspace NULL, misaligned (needs 256 B) or too small */
+  RLB_E_DEVICE = -5,      /* a HIP runtime call failed */
+  RLB_E_STATE = -6,       /* call not valid in this state (e.g. rlb_grad without tape) */
+  RLB_E_UNSUPPORTED = -7  /* valid request this build does not provide */
+} rlb_status;
+
+enum { RLB_PERIODIC = 0, RLB_ZERO_GRADIENT = 1 };
+enum { RLB_FP64 = 0, RLB_FP32 = 1 };
+
+/* One lattice (or one member of a batch). */
+typedef struct {
+  int32_t nx, ny, nz;  /* cells per axis, each >= 1 */
+  int32_t bc[3];       /* RLB_PERIODIC or RLB_ZERO_GRADIENT for x, y, z. Zero-gradient
+                          is the reading of the paper's "open" boundaries: the pull
+                          source coordinate is clamped into [0, N-1]. */
+  double tau_f;        /* f relaxation time, Eq. (5) */
+  double tau_v;        /* shear rows (3p_xx, p_ww, p_xy, p_yz, p_xz), Eq. (31) */
+  double tau_e;        /* energy row e (bulk viscosity), Eq. (31) */
+  double tau_eps;      /* energy-square row eps, Eq. (31) */
+  double tau_q;        /* ghost rows (q, 3pi_xx, pi_ww, m); <= 0 means tau_q = tau_v */
+} rlb_params;
+
+typedef struct {
+  int32_t precision;   /* RLB_FP32 or RLB_FP64: storage and collision precision of
+                          the populations. Recovery, moment sums and reductions are
+                          FP64 in both. */
+  int32_t ckpt_every;  /* 0: no tape. K > 0: keep the g populations every K steps
+                          so that rlb_grad can run (single-member handles only). */
+  int32_t tape_steps;  /* with ckpt_every > 0: the largest step count rlb_grad can
+                          differentiate (steps taken beyond it disable rlb_grad). */
+  int32_t diag_every;  /* 0: none. D > 0: every D-th step (and the last step of each
+                          rlb_step call) also leaves per-block FP64 partial sums of
+                          the conservation moments, read by rlb_diagnostics. */
+} rlb_options;
+
+typedef struct rlb_sim* rlb_handle;
+
+/* Bytes of device workspace rlb_init needs for these members and options.
+ * members: host array of n_members (>= 1) lattices. opt: host, non-NULL. */
+rlb_status rlb_workspace_size(const rlb_params* members, int32_t n_members,
+                              const rlb_options* opt, size_t* bytes);
+
+/* Create a simulation and set the state at t = 0 to the equilibria of the
+ * initial fields: f = f_eq(n0, u0) (Eq. 7), g = g_eq(eps0, eps0/3, u0)
+ * (Eqs. 8-9).
+ *   n0, eps0: ncells doubles each; u0: 3 * ncells doubles (u_x, u_y, u_z planes).
+ *   fields_on_device: 1 if n0/eps0/u0 are device pointers, 0 for host.
+ *   workspace: device, 256-byte aligned, at least rlb_workspace_size bytes.
+ *   hip_stream: hipStream_t (NULL = null stream); every later call uses it.
+ * Validation (before any device work): dims >= 1, bc in {0, 1}, every tau > 1/2
+ * and finite; every cell n0 >= 0, eps0 > 0, |u0| < 1 (finite). On error *out is
+ * NULL. The fields are only read during this call. */
+rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_members,
+                    const rlb_options* opt, const double* n0, const double* eps0,
+                    const double* u0, int32_t fields_on_device, void* workspace,
+                    size_t workspace_bytes, void* hip_stream);
+
+/* Advance every member by nsteps >= 0 steps, asynchronously on the stream.
+ * Single-member lattices run one fused kernel launch per step; batches (and
+ * small single lattices) run all nsteps inside one persistent launch per
+ * member group, replayed from a HIP graph. No validation per step: cells that
+ * become inadmissible (E <= 0 or |M| >= E) keep their populations uncollided
+ * and are counted; the count is reported by rlb_moments/rlb_diagnostics. */
+rlb_status rlb_step(rlb_handle h, int32_t nsteps);
+
+/* Fields of the current state (Eq. 10 sums + recovery, FP64) and the lattice
+ * sums {sum n gamma, sum (sigma - P), sum sigma u_x, sum sigma u_y, sum sigma u_z}.
+ * Any output pointer may be NULL (skipped). Scalar outputs: ncells doubles;
+ * u: 3 * ncells. out_on_device: 1 if the field pointers are device memory
+ * (sums and n_unphysical are always host). n_unphysical: host int64, the
+ * number of inadmissible cell-updates since rlb_init (their fields are NaN).
+ * Synchronises the stream. Returns RLB_E_UNPHYSICAL when that count is > 0
+ * (outputs are still written). */
+rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* gamma,
+                       double* u, double sums[5], int64_t* n_unphysical,
+                       int32_t out_on_device);
+
+/* FP64 lattice sums of the latest diagnostics step (see diag_every), and the
+ * step index they belong to (the sums of the populations streamed into that
+ * step, i.e. the conserved totals after it up to rounding). Host outputs;
+ * synchronises. RLB_E_STATE if no diagnostics step has run. */
+rlb_status rlb_diagnostics(rlb_handle h, double sums[5], int64_t* step,
+                           int64_t* n_unphysical);
+
+/* Copy the current populations out as FP64: f and g are each 19 * ncells
+ * doubles, population a of cell c at [a * ncells + c]. Either may be NULL.
+ * out_on_device as in rlb_moments. Synchronises. */
+rlb_status rlb_populations(rlb_handle h, double* f, double* g, int32_t out_on_device);
+
+/* Adjoint of the whole run (rlb_init + every rlb_step since), by reverse
+ * sweeps over checkpointed segments with recomputation. Given the gradient
+ * of a loss with respect to the current velocity and energy density fields,
+ *   dL_du: 3 * ncells, dL_deps: ncells,
+ * returns dL_dtau = {dL/dtau_v, dL/dtau_e, dL/dtau_eps} (host, 3 doubles),
+ * dL_deps0 (ncells) and dL_du0 (3 * ncells) for the initial fields.
+ * tau_q <= 0 ties the ghost rows to tau_v, and then their contribution is part
+ * of dL/dtau_v. Only g enters (u and eps never depend on f). io_on_device as
+ * in rlb_moments. Requires ckpt_every > 0 and steps taken <= tape_steps,
+ * else RLB_E_STATE. Does not change the forward state. Synchronises. */
+rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
+                    double dL_dtau[3], double* dL_deps0, double* dL_du0,
+                    int32_t io_on_device);
+
+/* Kernel variants (block shape x cells per thread) of the path this handle
+ * dispatches to. rlb_tune times every variant with HIP events on trial steps
+ * that read the current state and write only the spare buffer (the state is
+ * unchanged), selects the fastest, and returns all timings (ms per step,
+ * host array of rlb_num_variants doubles, may be NULL). */
+rlb_status rlb_num_variants(rlb_handle h, int32_t* count);
+rlb_status rlb_variant_name(rlb_handle h, int32_t variant, char* buf, size_t buflen);
+rlb_status rlb_set_variant(rlb_handle h, int32_t variant);
+rlb_status rlb_get_variant(rlb_handle h, int32_t* variant);
+rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
+                    double* ms_per_step);
+
+/* Step count since rlb_init, and the name of the kernel rlb_step launches. */
+rlb_status rlb_info(rlb_handle h, int64_t* steps, char* kernel_name, size_t buflen);
+
+/* Release the handle (no device memory is freed: the workspace is the
+ * caller's). Waits for the handle's queued work. NULL is ignored. */
+void rlb_free(rlb_handle h);
+
+const char* rlb_status_string(rlb_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLB_H */

@@ -1,0 +1,682 @@
+// C ABI of the relativistic lattice Boltzmann library (include/rlb.h):
+// argument validation, workspace carving, dispatch, graphs, autotuning.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rlb.h"
+#include "adjoint.hpp"
+#include "internal.hpp"
+
+using rlb::LatticeGeom;
+using rlb::MemberDesc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+// A single lattice at least this large runs one fused launch per step; smaller
+// lattices and batches run the persistent per-member kernel.
+constexpr int64_t kLatticeMinCells = 16384;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+  int64_t ncells = 0, cs = 0;
+  size_t esz = 0;
+  size_t off_descs = 0, off_small = 0, off_partials = 0, off_buf0 = 0, off_buf1 = 0;
+  size_t off_stage = 0, off_tape = 0, total = 0;
+  int max_parts = 0;
+  rlb::TapeLayout tape;
+};
+
+bool finite_tau(double t) { return std::isfinite(t) && t > 0.5; }
+
+rlb_status check_members(const rlb_params* m, int32_t n, int64_t* ncells) {
+  if (!m || n < 1) return RLB_E_ARG;
+  int64_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    const rlb_params& p = m[i];
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return RLB_E_ARG;
+    for (int k = 0; k < 3; ++k)
+      if (p.bc[k] != RLB_PERIODIC && p.bc[k] != RLB_ZERO_GRADIENT) return RLB_E_ARG;
+    const int64_t c = (int64_t)p.nx * p.ny * p.nz;
+    if (c >= (int64_t(1) << 31)) return RLB_E_UNSUPPORTED;
+    tot += c;
+  }
+  for (int i = 0; i < n; ++i) {
+    const rlb_params& p = m[i];
+    if (!finite_tau(p.tau_f) || !finite_tau(p.tau_v) || !finite_tau(p.tau_e) ||
+        !finite_tau(p.tau_eps))
+      return RLB_E_TAU;
+    if (p.tau_q > 0.0 && !finite_tau(p.tau_q)) return RLB_E_TAU;
+    if (std::isnan(p.tau_q)) return RLB_E_TAU;
+  }
+  *ncells = tot;
+  return RLB_OK;
+}
+
+bool lattice_path(int32_t n_members, int64_t ncells) {
+  return n_members == 1 && ncells >= kLatticeMinCells;
+}
+
+rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, Layout& L) {
+  if (!opt) return RLB_E_ARG;
+  if (opt->precision != RLB_FP32 && opt->precision != RLB_FP64) return RLB_E_ARG;
+  if (opt->ckpt_every < 0 || opt->tape_steps < 0 || opt->diag_every < 0) return RLB_E_ARG;
+  rlb_status st = check_members(m, n, &L.ncells);
+  if (st != RLB_OK) return st;
+  if (opt->ckpt_every > 0 && n != 1) return RLB_E_UNSUPPORTED;
+  L.esz = opt->precision == RLB_FP32 ? 4 : 8;
+  // Plane stride: a multiple of 64 elements plus 64 more, so that planes of a
+  // power-of-two lattice do not all start on the same HBM channel (measured:
+  // about 3 % faster at 256^3 than unpadded planes).
+  L.cs = (L.ncells + 63) / 64 * 64 + 64;
+  // every population byte offset of a plane is a 32-bit quantity in the kernels
+  if ((uint64_t)L.cs * L.esz >= (uint64_t(1) << 32)) return RLB_E_UNSUPPORTED;
+  int parts = std::max<int64_t>(n, (L.ncells + 255) / 256 > 65536 ? 65536 : (L.ncells + 255) / 256);
+  if (lattice_path(n, L.ncells)) {
+    LatticeGeom g{};
+    g.nx = m[0].nx;
+    g.ny = m[0].ny;
+    g.nz = m[0].nz;
+    for (int v = 0; v < rlb::num_lattice_variants(); ++v)
+      parts = std::max(parts, rlb::lattice_partials(v, g));
+  }
+  parts = std::max<int64_t>(parts, (int64_t)n * rlb::kRefBlocks);
+  L.max_parts = std::max(parts, 1);
+  size_t o = 0;
+  L.off_descs = o;
+  o = align_up(o + sizeof(MemberDesc) * n);
+  L.off_small = o;
+  o = align_up(o + 1024);
+  L.off_partials = o;
+  o = align_up(o + sizeof(double) * 5 * (size_t)L.max_parts);
+  const size_t buf = 38 * (size_t)L.cs * L.esz;
+  L.off_buf0 = o;
+  o = align_up(o + buf);
+  L.off_buf1 = o;
+  o = align_up(o + buf);
+  L.off_stage = o;
+  o = align_up(o + sizeof(double) * 8 * (size_t)L.ncells);
+  L.off_tape = o;
+  if (opt->ckpt_every > 0) {
+    L.tape = rlb::tape_layout(L.ncells, L.cs, L.esz, opt->ckpt_every, opt->tape_steps,
+                              L.max_parts);
+    o = align_up(o + L.tape.total);
+  }
+  L.total = o;
+  return RLB_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct rlb_sim {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int precision = RLB_FP32;
+  rlb_options opt{};
+  int n_members = 0;
+  std::vector<rlb_params> params;
+  std::vector<MemberDesc> descs;  // host copy, refs filled at init
+  Layout L;
+  char* ws = nullptr;
+  MemberDesc* d_descs = nullptr;
+  double* d_small = nullptr;  // [0..4] sums out, [8..] scratch
+  unsigned long long* d_bad = nullptr;
+  unsigned long long* d_count = nullptr;
+  unsigned long long* d_bad_save = nullptr;
+  double* d_partials = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  double* d_stage = nullptr;
+  int cur = 0;
+  bool lattice = false;
+  LatticeGeom geom{};
+  int variant = 0;
+  int64_t steps = 0;
+  int64_t diag_step = -1;
+  int diag_parts = 0;
+  // persistent-kernel graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t gnode = nullptr;
+  int graph_variant = -1;
+  rlb::MemberLaunch margs{};
+  // tape
+  rlb::Tape tape{};
+  bool tape_ok = false;
+};
+
+namespace {
+
+rlb_status dev_err(hipError_t e) { return e == hipSuccess ? RLB_OK : RLB_E_DEVICE; }
+
+#define RLB_HIP(call)                              \
+  do {                                             \
+    hipError_t _e = (call);                        \
+    if (_e != hipSuccess) return RLB_E_DEVICE;     \
+  } while (0)
+
+void* state_buf(rlb_sim* h) { return h->buf[h->cur]; }
+void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
+
+rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
+  return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
+                                          h->d_partials, h->d_bad, h->stream));
+}
+
+// Persistent member kernel through its graph (built on first use; later calls
+// only update the node's arguments).
+rlb_status launch_members_graph(rlb_sim* h, int nsteps, int pingpong, void* a, void* b,
+                                int diag_every, int64_t step0) {
+  rlb::MemberLaunch& m = h->margs;
+  m.descs = h->d_descs;
+  m.bufA = a;
+  m.bufB = b;
+  m.cs = h->L.cs;
+  m.nsteps = nsteps;
+  m.pingpong = pingpong;
+  m.diag_every = diag_every;
+  m.step0 = step0;
+  m.partials = h->d_partials;
+  m.bad = h->d_bad;
+  const void* func;
+  dim3 block;
+  RLB_HIP(rlb::member_kernel(h->precision, h->variant, &func, &block));
+  void* args[] = {&h->margs};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(func);
+  kp.gridDim = dim3(h->n_members, 1, 1);
+  kp.blockDim = block;
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  if (h->gexec && h->graph_variant != h->variant) {
+    (void)hipGraphExecDestroy(h->gexec);
+    (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+  }
+  if (!h->gexec) {
+    RLB_HIP(hipGraphCreate(&h->graph, 0));
+    RLB_HIP(hipGraphAddKernelNode(&h->gnode, h->graph, nullptr, 0, &kp));
+    RLB_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    h->graph_variant = h->variant;
+  } else {
+    RLB_HIP(hipGraphExecKernelNodeSetParams(h->gexec, h->gnode, &kp));
+  }
+  RLB_HIP(hipGraphLaunch(h->gexec, h->stream));
+  return RLB_OK;
+}
+
+// Advance n steps without taping.
+rlb_status advance(rlb_sim* h, int32_t n) {
+  if (n <= 0) return RLB_OK;
+  const int D = h->opt.diag_every;
+  if (h->lattice) {
+    for (int32_t i = 0; i < n; ++i) {
+      const int64_t s = h->steps + 1;
+      const bool diag = D > 0 && (s % D == 0 || i == n - 1);
+      rlb_status st = launch_lattice_step(h, h->variant, diag, state_buf(h), spare_buf(h));
+      if (st != RLB_OK) return st;
+      if (diag) {
+        h->diag_step = s;
+        h->diag_parts = rlb::lattice_partials(h->variant, h->geom);
+      }
+      h->cur = 1 - h->cur;
+      h->steps = s;
+    }
+    return RLB_OK;
+  }
+  rlb_status st = launch_members_graph(h, n, 1, state_buf(h), spare_buf(h), D, h->steps);
+  if (st != RLB_OK) return st;
+  if (D > 0) {
+    h->diag_step = h->steps + n;
+    h->diag_parts = h->n_members;
+  }
+  h->steps += n;
+  if (n & 1) h->cur = 1 - h->cur;
+  return RLB_OK;
+}
+
+rlb_status copy_fields_in(rlb_sim* h, const double* n0, const double* eps0, const double* u0,
+                          int on_device, const double** dn, const double** de,
+                          const double** du) {
+  const int64_t nc = h->L.ncells;
+  if (on_device) {
+    *dn = n0;
+    *de = eps0;
+    *du = u0;
+    return RLB_OK;
+  }
+  double* s = h->d_stage;
+  RLB_HIP(hipMemcpyAsync(s, n0, sizeof(double) * nc, hipMemcpyHostToDevice, h->stream));
+  RLB_HIP(hipMemcpyAsync(s + nc, eps0, sizeof(double) * nc, hipMemcpyHostToDevice, h->stream));
+  RLB_HIP(
+      hipMemcpyAsync(s + 2 * nc, u0, sizeof(double) * 3 * nc, hipMemcpyHostToDevice, h->stream));
+  *dn = s;
+  *de = s + nc;
+  *du = s + 2 * nc;
+  return RLB_OK;
+}
+
+bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int64_t nc) {
+  for (int64_t i = 0; i < nc; ++i) {
+    const double uu = u0[i] * u0[i] + u0[nc + i] * u0[nc + i] + u0[2 * nc + i] * u0[2 * nc + i];
+    if (!(eps0[i] > 0.0) || !(n0[i] >= 0.0) || !(uu < 1.0) || !std::isfinite(n0[i]) ||
+        !std::isfinite(eps0[i]))
+      return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* rlb_status_string(rlb_status s) {
+  switch (s) {
+    case RLB_OK: return "ok";
+    case RLB_E_ARG: return "invalid argument";
+    case RLB_E_TAU: return "relaxation time must be finite and > 1/2";
+    case RLB_E_UNPHYSICAL: return "inadmissible cell (eps <= 0, n < 0, |u| >= 1 or E <= 0, |M| >= E)";
+    case RLB_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case RLB_E_DEVICE: return "HIP runtime error";
+    case RLB_E_STATE: return "call not valid in the current state";
+    case RLB_E_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+rlb_status rlb_workspace_size(const rlb_params* members, int32_t n_members,
+                              const rlb_options* opt, size_t* bytes) {
+  if (!bytes) return RLB_E_ARG;
+  Layout L;
+  rlb_status st = make_layout(members, n_members, opt, L);
+  if (st != RLB_OK) return st;
+  *bytes = L.total;
+  return RLB_OK;
+}
+
+rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_members,
+                    const rlb_options* opt, const double* n0, const double* eps0,
+                    const double* u0, int32_t fields_on_device, void* workspace,
+                    size_t workspace_bytes, void* hip_stream) {
+  if (!out) return RLB_E_ARG;
+  *out = nullptr;
+  Layout L;
+  rlb_status st = make_layout(members, n_members, opt, L);
+  if (st != RLB_OK) return st;
+  if (!n0 || !eps0 || !u0) return RLB_E_ARG;
+  if (fields_on_device != 0 && fields_on_device != 1) return RLB_E_ARG;
+  if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
+    return RLB_E_WORKSPACE;
+  if (!fields_on_device && !host_fields_ok(n0, eps0, u0, L.ncells)) return RLB_E_UNPHYSICAL;
+
+  rlb_sim* h = new (std::nothrow) rlb_sim();
+  if (!h) return RLB_E_ARG;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return RLB_E_DEVICE;
+  }
+  h->stream = (hipStream_t)hip_stream;
+  h->precision = opt->precision;
+  h->opt = *opt;
+  h->n_members = n_members;
+  h->params.assign(members, members + n_members);
+  h->L = L;
+  h->ws = (char*)workspace;
+  h->d_descs = (MemberDesc*)(h->ws + L.off_descs);
+  h->d_small = (double*)(h->ws + L.off_small);
+  h->d_bad = (unsigned long long*)(h->d_small + 16);
+  h->d_count = h->d_bad + 1;
+  h->d_bad_save = h->d_bad + 2;
+  h->d_partials = (double*)(h->ws + L.off_partials);
+  h->buf[0] = h->ws + L.off_buf0;
+  h->buf[1] = h->ws + L.off_buf1;
+  h->d_stage = (double*)(h->ws + L.off_stage);
+  h->lattice = lattice_path(n_members, L.ncells);
+  h->variant = h->lattice ? 3 : 2;
+
+  auto fail = [&](rlb_status s) {
+    delete h;
+    return s;
+  };
+  // member descriptors (refs are filled on the device)
+  h->descs.resize(n_members);
+  int64_t off = 0;
+  for (int i = 0; i < n_members; ++i) {
+    const rlb_params& p = members[i];
+    MemberDesc& d = h->descs[i];
+    std::memset(&d, 0, sizeof(d));
+    d.offset = off;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nz = p.nz;
+    d.ncells = p.nx * p.ny * p.nz;
+    d.bcx = p.bc[0];
+    d.bcy = p.bc[1];
+    d.bcz = p.bc[2];
+    const double tq = p.tau_q > 0.0 ? p.tau_q : p.tau_v;
+    d.rt.w_f = 1.0 / p.tau_f;
+    d.rt.s_e = 1.0 / p.tau_e;
+    d.rt.s_eps = 1.0 / p.tau_eps;
+    d.rt.s_q = 1.0 / tq;
+    d.rt.s_v = 1.0 / p.tau_v;
+    off += d.ncells;
+  }
+  const double *dn, *de, *du;
+  if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess) return fail(RLB_E_DEVICE);
+  if (copy_fields_in(h, n0, eps0, u0, fields_on_device, &dn, &de, &du) != RLB_OK)
+    return fail(RLB_E_DEVICE);
+  if (fields_on_device) {
+    if (rlb::launch_validate(dn, de, du, L.ncells, h->d_count, h->stream) != hipSuccess)
+      return fail(RLB_E_DEVICE);
+    unsigned long long cnt = 0;
+    if (hipMemcpyAsync(&cnt, h->d_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess)
+      return fail(RLB_E_DEVICE);
+    if (cnt) return fail(RLB_E_UNPHYSICAL);
+  }
+  if (hipMemcpyAsync(h->d_descs, h->descs.data(), sizeof(MemberDesc) * n_members,
+                     hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
+  if (rlb::launch_member_refs(h->d_descs, n_members, dn, de, du, L.ncells, h->d_partials,
+                              h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
+  if (rlb::launch_init(h->precision, h->buf[0], L.cs, h->d_descs, n_members, dn, de, du,
+                       L.ncells, h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
+  if (hipMemcpyAsync(h->descs.data(), h->d_descs, sizeof(MemberDesc) * n_members,
+                     hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
+      hipStreamSynchronize(h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
+  if (h->lattice) {
+    const MemberDesc& d = h->descs[0];
+    h->geom.nx = d.nx;
+    h->geom.ny = d.ny;
+    h->geom.nz = d.nz;
+    h->geom.bcx = d.bcx;
+    h->geom.bcy = d.bcy;
+    h->geom.bcz = d.bcz;
+    h->geom.cs = L.cs;
+    h->geom.rt = d.rt;
+    h->geom.ref = d.ref;
+  }
+  h->cur = 0;
+  if (opt->ckpt_every > 0) {
+    rlb_status ts = rlb::tape_init(h->tape, L.tape, h->ws + L.off_tape, h->precision, L.ncells,
+                                   L.cs, opt->ckpt_every, opt->tape_steps, dn, de, du,
+                                   h->buf[0], h->stream);
+    if (ts != RLB_OK) return fail(ts);
+    h->tape_ok = true;
+  }
+  *out = h;
+  return RLB_OK;
+}
+
+rlb_status rlb_step(rlb_handle h, int32_t nsteps) {
+  if (!h || nsteps < 0) return RLB_E_ARG;
+  if (nsteps == 0) return RLB_OK;
+  DeviceGuard g(h->device);
+  if (!g.ok) return RLB_E_DEVICE;
+  if (h->opt.ckpt_every <= 0 || !h->tape_ok) return advance(h, nsteps);
+  // With a tape: stop at every checkpoint boundary and keep g.
+  const int K = h->opt.ckpt_every;
+  int32_t left = nsteps;
+  while (left > 0) {
+    int32_t chunk = (int32_t)std::min<int64_t>(left, K - (h->steps % K));
+    rlb_status st = advance(h, chunk);
+    if (st != RLB_OK) return st;
+    left -= chunk;
+    if (h->steps > h->opt.tape_steps) {
+      h->tape_ok = false;
+      return advance(h, left);
+    }
+    if (h->steps % K == 0) {
+      st = rlb::tape_checkpoint(h->tape, h->steps / K, state_buf(h), h->stream);
+      if (st != RLB_OK) return st;
+    }
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* gamma,
+                       double* u, double sums[5], int64_t* n_unphysical,
+                       int32_t out_on_device) {
+  if (!h) return RLB_E_ARG;
+  if (out_on_device != 0 && out_on_device != 1) return RLB_E_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return RLB_E_DEVICE;
+  const int64_t nc = h->L.ncells;
+  double* s = h->d_stage;
+  double *dn = n, *de = eps, *dP = P, *dg = gamma, *du = u;
+  if (!out_on_device) {
+    dn = n ? s : nullptr;
+    de = eps ? s + nc : nullptr;
+    dP = P ? s + 2 * nc : nullptr;
+    dg = gamma ? s + 3 * nc : nullptr;
+    du = u ? s + 4 * nc : nullptr;
+  }
+  int nparts = (int)std::min<int64_t>(std::max<int64_t>((nc + 255) / 256, 1), 65536);
+  nparts = std::min(nparts, h->L.max_parts);
+  RLB_HIP(rlb::launch_export(h->precision, state_buf(h), h->L.cs, h->d_descs, h->n_members, nc,
+                             dn, de, dP, dg, du, h->d_partials, nparts, h->stream));
+  RLB_HIP(rlb::launch_reduce(h->d_partials, nparts, h->d_small, h->stream));
+  double hs[5];
+  unsigned long long bad = 0;
+  RLB_HIP(hipMemcpyAsync(hs, h->d_small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+  if (!out_on_device) {
+    if (n) RLB_HIP(hipMemcpyAsync(n, dn, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream));
+    if (eps)
+      RLB_HIP(hipMemcpyAsync(eps, de, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream));
+    if (P) RLB_HIP(hipMemcpyAsync(P, dP, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream));
+    if (gamma)
+      RLB_HIP(hipMemcpyAsync(gamma, dg, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream));
+    if (u)
+      RLB_HIP(hipMemcpyAsync(u, du, sizeof(double) * 3 * nc, hipMemcpyDeviceToHost, h->stream));
+  }
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  if (sums) std::memcpy(sums, hs, sizeof(hs));
+  if (n_unphysical) *n_unphysical = (int64_t)bad;
+  return bad ? RLB_E_UNPHYSICAL : RLB_OK;
+}
+
+rlb_status rlb_diagnostics(rlb_handle h, double sums[5], int64_t* step, int64_t* n_unphysical) {
+  if (!h) return RLB_E_ARG;
+  if (h->diag_step < 0) return RLB_E_STATE;
+  DeviceGuard g(h->device);
+  if (!g.ok) return RLB_E_DEVICE;
+  RLB_HIP(rlb::launch_reduce(h->d_partials, h->diag_parts, h->d_small, h->stream));
+  double hs[5];
+  unsigned long long bad = 0;
+  RLB_HIP(hipMemcpyAsync(hs, h->d_small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  if (sums) std::memcpy(sums, hs, sizeof(hs));
+  if (step) *step = h->diag_step;
+  if (n_unphysical) *n_unphysical = (int64_t)bad;
+  return RLB_OK;
+}
+
+rlb_status rlb_populations(rlb_handle h, double* f, double* g, int32_t out_on_device) {
+  if (!h) return RLB_E_ARG;
+  if (out_on_device != 0 && out_on_device != 1) return RLB_E_ARG;
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return RLB_E_DEVICE;
+  const int64_t nc = h->L.ncells;
+  if (out_on_device) {
+    if (f)
+      RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
+                                            h->n_members, nc, 0, 19, f, h->stream));
+    if (g)
+      RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
+                                            h->n_members, nc, 19, 19, g, h->stream));
+  } else {
+    // staging holds 8 planes: convert f (then g) in chunks of up to 8 planes
+    double* s = h->d_stage;
+    for (int which = 0; which < 2; ++which) {
+      double* hostp = which ? g : f;
+      if (!hostp) continue;
+      for (int a0 = 0; a0 < 19; a0 += 8) {
+        const int na = std::min(8, 19 - a0);
+        RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
+                                              h->n_members, nc, which * 19 + a0, na, s,
+                                              h->stream));
+        RLB_HIP(hipMemcpyAsync(hostp + (size_t)a0 * nc, s, sizeof(double) * na * nc,
+                               hipMemcpyDeviceToHost, h->stream));
+        RLB_HIP(hipStreamSynchronize(h->stream));
+      }
+    }
+  }
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  return RLB_OK;
+}
+
+rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
+                    double dL_dtau[3], double* dL_deps0, double* dL_du0, int32_t io_on_device) {
+  if (!h || !dL_du || !dL_deps || !dL_dtau || !dL_deps0 || !dL_du0) return RLB_E_ARG;
+  if (io_on_device != 0 && io_on_device != 1) return RLB_E_ARG;
+  if (h->opt.ckpt_every <= 0 || !h->tape_ok) return RLB_E_STATE;
+  DeviceGuard g(h->device);
+  if (!g.ok) return RLB_E_DEVICE;
+  rlb::GradContext c{};
+  c.precision = h->precision;
+  c.ncells = h->L.ncells;
+  c.cs = h->L.cs;
+  c.desc = h->descs[0];
+  c.steps = h->steps;
+  c.lattice = h->lattice;
+  c.variant = h->variant;
+  c.d_descs = h->d_descs;
+  c.stage = h->d_stage;
+  c.stream = h->stream;
+  return rlb::tape_grad(h->tape, c, dL_du, dL_deps, dL_dtau, dL_deps0, dL_du0, io_on_device);
+}
+
+rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
+  if (!h || !count) return RLB_E_ARG;
+  *count = h->lattice ? rlb::num_lattice_variants() : rlb::num_member_variants();
+  return RLB_OK;
+}
+
+rlb_status rlb_variant_name(rlb_handle h, int32_t v, char* buf, size_t buflen) {
+  int32_t n;
+  if (rlb_num_variants(h, &n) != RLB_OK || !buf || buflen == 0) return RLB_E_ARG;
+  if (v < 0 || v >= n) return RLB_E_ARG;
+  const char* s = h->lattice ? rlb::lattice_kernel_name(h->precision, v)
+                             : rlb::member_kernel_name(h->precision, v);
+  std::snprintf(buf, buflen, "%s", s);
+  return RLB_OK;
+}
+
+rlb_status rlb_set_variant(rlb_handle h, int32_t v) {
+  int32_t n;
+  if (rlb_num_variants(h, &n) != RLB_OK) return RLB_E_ARG;
+  if (v < 0 || v >= n) return RLB_E_ARG;
+  h->variant = v;
+  return RLB_OK;
+}
+
+rlb_status rlb_get_variant(rlb_handle h, int32_t* v) {
+  if (!h || !v) return RLB_E_ARG;
+  *v = h->variant;
+  return RLB_OK;
+}
+
+rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
+                    double* ms_per_step) {
+  if (!h || trial_steps < 1) return RLB_E_ARG;
+  DeviceGuard g(h->device);
+  if (!g.ok) return RLB_E_DEVICE;
+  int32_t n;
+  rlb_num_variants(h, &n);
+  hipEvent_t e0, e1;
+  RLB_HIP(hipEventCreate(&e0));
+  RLB_HIP(hipEventCreate(&e1));
+  // trial steps must not count toward the inadmissible-cell total
+  RLB_HIP(hipMemcpyAsync(h->d_bad_save, h->d_bad, sizeof(unsigned long long),
+                         hipMemcpyDeviceToDevice, h->stream));
+  const int keep = h->variant;
+  int best = keep;
+  double best_ms = 1e300;
+  rlb_status st = RLB_OK;
+  for (int v = 0; v < n && st == RLB_OK; ++v) {
+    float ms = 0.0f;
+    h->variant = v;
+    for (int rep = 0; rep < 2 && st == RLB_OK; ++rep) {  // rep 0 warms up
+      if (hipEventRecord(e0, h->stream) != hipSuccess) st = RLB_E_DEVICE;
+      if (h->lattice) {
+        for (int i = 0; i < trial_steps && st == RLB_OK; ++i)
+          st = launch_lattice_step(h, v, false, state_buf(h), spare_buf(h));
+      } else if (st == RLB_OK) {
+        st = launch_members_graph(h, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0);
+      }
+      if (st == RLB_OK && hipEventRecord(e1, h->stream) != hipSuccess) st = RLB_E_DEVICE;
+      if (st == RLB_OK && hipEventSynchronize(e1) != hipSuccess) st = RLB_E_DEVICE;
+      if (st == RLB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = RLB_E_DEVICE;
+    }
+    const double per = (double)ms / trial_steps;
+    if (ms_per_step) ms_per_step[v] = per;
+    if (st == RLB_OK && per < best_ms) {
+      best_ms = per;
+      best = v;
+    }
+  }
+  (void)hipMemcpyAsync(h->d_bad, h->d_bad_save, sizeof(unsigned long long),
+                       hipMemcpyDeviceToDevice, h->stream);
+  (void)hipStreamSynchronize(h->stream);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->variant = (st == RLB_OK) ? best : keep;
+  if (best_variant) *best_variant = h->variant;
+  return st;
+}
+
+rlb_status rlb_info(rlb_handle h, int64_t* steps, char* kernel_name, size_t buflen) {
+  if (!h) return RLB_E_ARG;
+  if (steps) *steps = h->steps;
+  if (kernel_name && buflen)
+    std::snprintf(kernel_name, buflen, "%s",
+                  h->lattice ? rlb::lattice_kernel_name(h->precision, h->variant)
+                             : rlb::member_kernel_name(h->precision, h->variant));
+  return RLB_OK;
+}
+
+void rlb_free(rlb_handle h) {
+  if (!h) return;
+  {
+    DeviceGuard g(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    rlb::tape_release(h->tape);
+  }
+  delete h;
+}
+
+}  // extern "C"

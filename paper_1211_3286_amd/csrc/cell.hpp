@@ -1,0 +1,327 @@
+// Per-cell arithmetic of the relativistic MRT lattice Boltzmann step (device).
+//
+// The state of a cell is its 19 f and 19 g populations stored as deviations
+// from a rest reference state (n_r, P_r) of the member:
+//   f_a = w_a n_r + f~_a,   g_a = gref_a + g~_a,
+//   gref = (P_r, P_r/6 on the faces, P_r/12 on the edges) = g_eq(3 P_r, P_r, 0).
+// Storing the deviation keeps FP32 rounding relative to the (small) departure
+// from the reference instead of to the full population; it costs one add per
+// reference moment and nothing per population.
+//
+// Per cell (Sec. II and Sec. V.A of the paper):
+//   1. Eq. (10) sums in FP64: N = sum f (= n gamma), E = sum g (= sigma - P),
+//      M = sum e g (= sigma u).
+//   2. Recovery in FP64 with P = eps/3: u = 3 M / (2E + sqrt(4E^2 - 3|M|^2)),
+//      sigma = 4E / (3 + u^2), P = sigma (1 - u^2) / 4. A cell with E <= 0 or
+//      |M| >= E is inadmissible: it is left uncollided and reported.
+//   3. f: BGK, Eq. (5), with f_eq of Eq. (7) (n gamma = N).
+//   4. g: MRT, Eqs. (30), (35), in the orthogonal D3Q19 moment basis
+//      (rho, e, eps, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww,
+//      p_xy, p_yz, p_xz, m_x, m_y, m_z). M has integer entries, so m = M g and
+//      g* = g - M^-1 S (m - m_eq) are applied in factored form on the sums and
+//      differences of opposite populations, with the entries of M as
+//      instruction constants; M^-1 = M^T diag(1/|row|^2) (orthogonal rows).
+//      m_eq is evaluated in closed form from sigma, P, u (it equals M g_eq of
+//      Eqs. 8-9). The conserved rows (rho, j) keep m* = m (tau_sigma = tau_j = dt).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rlb {
+
+// Relaxation rates 1/tau of one member (Eq. 31 generalised to D3Q19).
+struct Rates {
+  double w_f;    // 1/tau_f   (f, Eq. 5)
+  double s_e;    // 1/tau_e   (e row)
+  double s_eps;  // 1/tau_eps (eps row)
+  double s_q;    // 1/tau_q   (q, 3pi_xx, pi_ww, m rows)
+  double s_v;    // 1/tau_v   (3p_xx, p_ww, p_xy, p_yz, p_xz rows)
+};
+
+// Rest reference state the populations are stored relative to.
+struct Ref {
+  double n;  // n_r
+  double P;  // P_r
+};
+
+// Conservation sums of one cell, FP64: N, E, Mx, My, Mz.
+struct Sums {
+  double v[5];
+};
+
+// Velocity set (order of rlb.h).
+__host__ __device__ constexpr int ex(int a) {
+  constexpr int t[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return t[a];
+}
+__host__ __device__ constexpr int ey(int a) {
+  constexpr int t[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return t[a];
+}
+__host__ __device__ constexpr int ez(int a) {
+  constexpr int t[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return t[a];
+}
+// Lattice weights 1/3, 1/18, 1/36 (rest, faces, edges).
+__host__ __device__ constexpr double weight(int a) {
+  return a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// Reference g populations in units of P_r.
+__host__ __device__ constexpr double gref_unit(int a) {
+  return a == 0 ? 1.0 : (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
+}
+
+// FP64 Eq. (10) sums of a cell from its stored deviations. fs and gs are the
+// plain sums of the stored f and g values (N = n_r + fs, E = 3 P_r + gs).
+template <typename C>
+__device__ __forceinline__ void cell_sums(const C (&f)[19], const C (&g)[19], const Ref& ref,
+                                          double& N, double& E, double& Mx, double& My,
+                                          double& Mz, double& fs, double& gs) {
+  fs = 0.0;
+#pragma unroll
+  for (int a = 0; a < 19; ++a) fs += (double)f[a];
+  N = ref.n + fs;
+  double gd[19];
+#pragma unroll
+  for (int a = 0; a < 19; ++a) gd[a] = (double)g[a];
+  // opposite pairs (a, a+1) for a odd
+  const double S1 = gd[1] + gd[2], S3 = gd[3] + gd[4], S5 = gd[5] + gd[6];
+  const double S7 = gd[7] + gd[8], S9 = gd[9] + gd[10], S11 = gd[11] + gd[12];
+  const double S13 = gd[13] + gd[14], S15 = gd[15] + gd[16], S17 = gd[17] + gd[18];
+  const double D1 = gd[1] - gd[2], D3 = gd[3] - gd[4], D5 = gd[5] - gd[6];
+  const double D7 = gd[7] - gd[8], D9 = gd[9] - gd[10], D11 = gd[11] - gd[12];
+  const double D13 = gd[13] - gd[14], D15 = gd[15] - gd[16], D17 = gd[17] - gd[18];
+  gs = gd[0] + ((S1 + S3) + (S5 + S7)) + ((S9 + S11) + (S13 + S15)) + S17;
+  E = 3.0 * ref.P + gs;
+  Mx = D1 + (D7 + D9) + (D11 + D13);
+  My = D3 + (D7 - D9) + (D15 + D17);
+  Mz = D5 + (D11 - D13) + (D15 - D17);
+}
+
+// Recovery (FP64). Returns false for an inadmissible cell.
+struct Macro {
+  double ux, uy, uz, u2, sigma, P;
+};
+
+__device__ __forceinline__ bool recover(double E, double Mx, double My, double Mz, Macro& m) {
+  const double M2 = Mx * Mx + My * My + Mz * Mz;
+  const bool ok = (E > 0.0) && (M2 < E * E);
+  const double Es = ok ? E : 1.0;
+  const double M2s = ok ? M2 : 0.0;
+  const double q = 3.0 / (2.0 * Es + sqrt(4.0 * Es * Es - 3.0 * M2s));
+  m.ux = ok ? q * Mx : 0.0;
+  m.uy = ok ? q * My : 0.0;
+  m.uz = ok ? q * Mz : 0.0;
+  m.u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  m.sigma = 4.0 * Es / (3.0 + m.u2);
+  m.P = 0.25 * m.sigma * (1.0 - m.u2);
+  return ok;
+}
+
+// One collision in place on the stored deviations. Returns admissibility.
+// sums receives the FP64 Eq. (10) sums of the incoming populations.
+template <typename C>
+__device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt, const Ref& ref,
+                                        Sums& sums) {
+  double N, E, Mx, My, Mz, fs, gs;
+  cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
+  sums.v[0] = N;
+  sums.v[1] = E;
+  sums.v[2] = Mx;
+  sums.v[3] = My;
+  sums.v[4] = Mz;
+  Macro mac;
+  const bool ok = recover(E, Mx, My, Mz, mac);
+  if (!ok) return false;
+
+  // ---------------- f: BGK (Eq. 5), f_eq of Eq. (7) ----------------
+  {
+    const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)mac.u2;
+    const C Nc = (C)N;
+    const C b = (C)(N - ref.n) - C(1.5) * Nc * uu;  // deviation part of w-bracket
+    const C a3 = C(3.0) * Nc, a45 = C(4.5) * Nc;
+    const C wf = (C)rt.w_f;
+    const C w0 = C(1.0 / 3.0), w1 = C(1.0 / 18.0), w2 = C(1.0 / 36.0);
+    C eu[19];
+    eu[0] = C(0.0);
+    eu[1] = ux;
+    eu[2] = -ux;
+    eu[3] = uy;
+    eu[4] = -uy;
+    eu[5] = uz;
+    eu[6] = -uz;
+    eu[7] = ux + uy;
+    eu[8] = -(ux + uy);
+    eu[9] = ux - uy;
+    eu[10] = -(ux - uy);
+    eu[11] = ux + uz;
+    eu[12] = -(ux + uz);
+    eu[13] = ux - uz;
+    eu[14] = -(ux - uz);
+    eu[15] = uy + uz;
+    eu[16] = -(uy + uz);
+    eu[17] = uy - uz;
+    eu[18] = -(uy - uz);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      const C w = a == 0 ? w0 : (a < 7 ? w1 : w2);
+      const C feq = w * (b + a3 * eu[a] + a45 * eu[a] * eu[a]);
+      f[a] = f[a] + wf * (feq - f[a]);
+    }
+  }
+
+  // ---------------- g: MRT (Eqs. 30, 31, 35) ----------------
+  {
+    const C g0 = g[0];
+    const C S1 = g[1] + g[2], S3 = g[3] + g[4], S5 = g[5] + g[6];
+    const C S7 = g[7] + g[8], S9 = g[9] + g[10], S11 = g[11] + g[12];
+    const C S13 = g[13] + g[14], S15 = g[15] + g[16], S17 = g[17] + g[18];
+    const C D1 = g[1] - g[2], D3 = g[3] - g[4], D5 = g[5] - g[6];
+    const C D7 = g[7] - g[8], D9 = g[9] - g[10], D11 = g[11] - g[12];
+    const C D13 = g[13] - g[14], D15 = g[15] - g[16], D17 = g[17] - g[18];
+    const C Sf = S1 + S3 + S5;
+    const C Exy = S7 + S9, Exz = S11 + S13, Eyz = S15 + S17;
+    const C Se = Exy + Exz + Eyz;
+
+    // non-conserved moments of the stored deviations
+    const C m_e = C(-30.0) * g0 - C(11.0) * Sf + C(8.0) * Se;
+    const C m_eps = C(12.0) * g0 - C(4.0) * Sf + Se;
+    const C xyz_p = Exy + Exz - C(2.0) * Eyz;
+    const C m_3pxx = C(2.0) * S1 - S3 - S5 + xyz_p;
+    const C m_3pixx = C(-4.0) * S1 + C(2.0) * S3 + C(2.0) * S5 + xyz_p;
+    const C m_pww = S3 - S5 + Exy - Exz;
+    const C m_piww = C(-2.0) * S3 + C(2.0) * S5 + Exy - Exz;
+    const C m_pxy = S7 - S9, m_pxz = S11 - S13, m_pyz = S15 - S17;
+    const C m_qx = C(-4.0) * D1 + D7 + D9 + D11 + D13;
+    const C m_qy = C(-4.0) * D3 + D7 - D9 + D15 + D17;
+    const C m_qz = C(-4.0) * D5 + D11 - D13 + D15 - D17;
+    const C m_mx = D7 + D9 - D11 - D13;
+    const C m_my = -D7 + D9 + D15 + D17;
+    const C m_mz = D11 - D13 - D15 + D17;
+
+    // equilibrium moments minus the reference's (closed forms of M g_eq)
+    const double sd = mac.sigma, Pd = mac.P, u2d = mac.u2;
+    const C meq_e = (C)(19.0 * sd * u2d + 87.0 * Pd - 30.0 * sd + 33.0 * ref.P);
+    const C meq_eps = (C)(12.0 * sd - 39.0 * Pd - 5.5 * sd * u2d - 9.0 * ref.P);
+    const C sg = (C)sd;
+    const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)u2d;
+    const C sux = sg * ux, suy = sg * uy, suz = sg * uz;
+    const C meq_3pxx = sg * (C(3.0) * ux * ux - uu);
+    const C meq_pww = sg * (uy * uy - uz * uz);
+    const C meq_q = C(-2.0 / 3.0);
+
+    // c_k = s_k (m_k - m_eq,k) / |row_k|^2
+    const C se = (C)rt.s_e, seps = (C)rt.s_eps, sq = (C)rt.s_q, sv = (C)rt.s_v;
+    const C ce = se * (m_e - meq_e) * C(1.0 / 2394.0);
+    const C ceps = seps * (m_eps - meq_eps) * C(1.0 / 252.0);
+    const C cqx = sq * (m_qx - meq_q * sux) * C(1.0 / 40.0);
+    const C cqy = sq * (m_qy - meq_q * suy) * C(1.0 / 40.0);
+    const C cqz = sq * (m_qz - meq_q * suz) * C(1.0 / 40.0);
+    const C cp = sv * (m_3pxx - meq_3pxx) * C(1.0 / 36.0);
+    const C cpi = sq * (m_3pixx + C(0.5) * meq_3pxx) * C(1.0 / 72.0);
+    const C cw = sv * (m_pww - meq_pww) * C(1.0 / 12.0);
+    const C cwpi = sq * (m_piww + C(0.5) * meq_pww) * C(1.0 / 24.0);
+    const C cxy = sv * (m_pxy - sux * uy) * C(0.25);
+    const C cxz = sv * (m_pxz - sux * uz) * C(0.25);
+    const C cyz = sv * (m_pyz - suy * uz) * C(0.25);
+    const C cmx = sq * m_mx * C(0.125);
+    const C cmy = sq * m_my * C(0.125);
+    const C cmz = sq * m_mz * C(0.125);
+
+    // g* = g - M^T c
+    const C face = C(-11.0) * ce - C(4.0) * ceps;
+    const C ev_x = face + C(2.0) * cp - C(4.0) * cpi;
+    const C ev_y = face - cp + C(2.0) * cpi + cw - C(2.0) * cwpi;
+    const C ev_z = face - cp + C(2.0) * cpi - cw + C(2.0) * cwpi;
+    const C edge = C(8.0) * ce + ceps;
+    const C ev_xy = edge + cp + cpi + cw + cwpi;
+    const C ev_xz = edge + cp + cpi - cw - cwpi;
+    const C ev_yz = edge - C(2.0) * (cp + cpi);
+    const C od_x = C(-4.0) * cqx, od_y = C(-4.0) * cqy, od_z = C(-4.0) * cqz;
+    const C o7 = cqx + cqy + cmx - cmy;
+    const C o9 = cqx - cqy + cmx + cmy;
+    const C o11 = cqx + cqz - cmx + cmz;
+    const C o13 = cqx - cqz - cmx - cmz;
+    const C o15 = cqy + cqz + cmy - cmz;
+    const C o17 = cqy - cqz + cmy + cmz;
+
+    g[0] = g0 - (C(-30.0) * ce + C(12.0) * ceps);
+    g[1] = g[1] - (ev_x + od_x);
+    g[2] = g[2] - (ev_x - od_x);
+    g[3] = g[3] - (ev_y + od_y);
+    g[4] = g[4] - (ev_y - od_y);
+    g[5] = g[5] - (ev_z + od_z);
+    g[6] = g[6] - (ev_z - od_z);
+    g[7] = g[7] - (ev_xy + cxy + o7);
+    g[8] = g[8] - (ev_xy + cxy - o7);
+    g[9] = g[9] - (ev_xy - cxy + o9);
+    g[10] = g[10] - (ev_xy - cxy - o9);
+    g[11] = g[11] - (ev_xz + cxz + o11);
+    g[12] = g[12] - (ev_xz + cxz - o11);
+    g[13] = g[13] - (ev_xz - cxz + o13);
+    g[14] = g[14] - (ev_xz - cxz - o13);
+    g[15] = g[15] - (ev_yz + cyz + o15);
+    g[16] = g[16] - (ev_yz + cyz - o15);
+    g[17] = g[17] - (ev_yz - cyz + o17);
+    g[18] = g[18] - (ev_yz - cyz - o17);
+  }
+
+  // FP32 storage: the conserved sums of the rounded outputs differ from the
+  // incoming ones by a rounding residual that is not zero on average (it
+  // builds up linearly over steps). It is folded back, computed in FP64:
+  // momentum into g_1, g_3, g_5 (one population per axis), then particle
+  // number into f_0 and energy into g_0 (rest populations carry no momentum).
+  // What remains is one rounding per population, with no bias.
+  if constexpr (sizeof(C) == 4) {
+    double fo = 0.0;
+#pragma unroll
+    for (int a = 1; a < 19; ++a) fo += (double)f[a];
+    f[0] = (C)(fs - fo);
+    double gd[19];
+#pragma unroll
+    for (int a = 1; a < 19; ++a) gd[a] = (double)g[a];
+    const double mx = (gd[1] - gd[2]) + ((gd[7] - gd[8]) + (gd[9] - gd[10])) +
+                      ((gd[11] - gd[12]) + (gd[13] - gd[14]));
+    const double my = (gd[3] - gd[4]) + ((gd[7] - gd[8]) - (gd[9] - gd[10])) +
+                      ((gd[15] - gd[16]) + (gd[17] - gd[18]));
+    const double mz = (gd[5] - gd[6]) + ((gd[11] - gd[12]) - (gd[13] - gd[14])) +
+                      ((gd[15] - gd[16]) - (gd[17] - gd[18]));
+    g[1] = (C)(gd[1] + (Mx - mx));
+    g[3] = (C)(gd[3] + (My - my));
+    g[5] = (C)(gd[5] + (Mz - mz));
+    gd[1] = (double)g[1];
+    gd[3] = (double)g[3];
+    gd[5] = (double)g[5];
+    double go = 0.0;
+#pragma unroll
+    for (int a = 1; a < 19; ++a) go += gd[a];
+    g[0] = (C)(gs - go);
+  }
+  return true;
+}
+
+// Equilibrium deviations of a cell from its fields (init, Eqs. 7-9), FP64.
+__device__ __forceinline__ void equilibrium_dev(double n, double eps, double ux, double uy,
+                                                double uz, const Ref& ref, double (&f)[19],
+                                                double (&g)[19]) {
+  const double uu = ux * ux + uy * uy + uz * uz;
+  const double gam2 = 1.0 / (1.0 - uu);
+  const double N = n * sqrt(gam2);
+  const double P = eps / 3.0;
+  const double sigma = (eps + P) * gam2;
+#pragma unroll
+  for (int a = 0; a < 19; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy + ez(a) * uz;
+    const double w = weight(a);
+    f[a] = w * (N * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - ref.n);
+    double gv;
+    if (a == 0)
+      gv = w * (3.0 * sigma - 9.0 * P - 1.5 * sigma * uu);
+    else
+      gv = w * (3.0 * P + 3.0 * sigma * eu + 4.5 * sigma * eu * eu - 1.5 * sigma * uu);
+    g[a] = gv - gref_unit(a) * ref.P;
+  }
+}
+
+}  // namespace rlb

@@ -1,0 +1,88 @@
+// Host-side interfaces between the C ABI (api.cpp) and the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "cell.hpp"
+
+namespace rlb {
+
+// One lattice of a batch, as the kernels see it (device copy in the workspace).
+struct MemberDesc {
+  int64_t offset;  // first cell in the packed population planes
+  int32_t nx, ny, nz;
+  int32_t ncells;  // nx*ny*nz (members of the persistent path are < 2^31 cells)
+  int32_t bcx, bcy, bcz;
+  int32_t pad;
+  Rates rt;
+  Ref ref;
+};
+
+// Geometry of a single-lattice launch (the per-step fused kernel).
+struct LatticeGeom {
+  int32_t nx, ny, nz;
+  int32_t bcx, bcy, bcz;
+  int64_t cs;  // plane stride in elements
+  Rates rt;
+  Ref ref;
+};
+
+struct LatticeVariant {
+  int bx, by, cz;
+};
+struct MemberVariant {
+  int nt, cpt;
+};
+
+int num_lattice_variants();
+LatticeVariant lattice_variant(int i);
+int num_member_variants();
+MemberVariant member_variant(int i);
+
+// precision: 0 = FP64, 1 = FP32 (rlb.h).
+// Partial-sum blocks per member of the reference-state pass; the partials
+// buffer must hold n_members * kRefBlocks * 5 doubles.
+constexpr int kRefBlocks = 64;
+hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const double* n0,
+                              const double* eps0, const double* u0, int64_t ncells,
+                              double* parts, hipStream_t s);
+hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
+                           int64_t ncells, unsigned long long* count, hipStream_t s);
+hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
+                       int n_members, const double* n0, const double* eps0, const double* u0,
+                       int64_t ncells, hipStream_t s);
+hipError_t launch_step_lattice(int precision, int variant, bool diag, const void* src, void* dst,
+                               const LatticeGeom& g, double* partials,
+                               unsigned long long* bad, hipStream_t s);
+int lattice_partials(int variant, const LatticeGeom& g);  // number of blocks
+// Kernel function pointer and launch shape of the persistent member kernel
+// (for graph nodes). args must outlive the launch.
+struct MemberLaunch {
+  const MemberDesc* descs;
+  void* bufA;
+  void* bufB;
+  int64_t cs;
+  int32_t nsteps;
+  int32_t pingpong;
+  int32_t diag_every;
+  int32_t pad;
+  int64_t step0;
+  double* partials;
+  unsigned long long* bad;
+};
+hipError_t member_kernel(int precision, int variant, const void** func, dim3* block);
+hipError_t launch_step_members(int precision, int variant, int n_members, const MemberLaunch& a,
+                               hipStream_t s);
+hipError_t launch_export(int precision, const void* state, int64_t cs, const MemberDesc* descs,
+                         int n_members, int64_t ncells, double* n, double* eps, double* P,
+                         double* gamma, double* u, double* partials, int nparts, hipStream_t s);
+hipError_t launch_population_planes(int precision, const void* state, int64_t cs,
+                                    const MemberDesc* descs, int n_members, int64_t ncells,
+                                    int p0, int np, double* out, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int nparts, double* out5, hipStream_t s);
+const char* lattice_kernel_name(int precision, int variant);
+const char* member_kernel_name(int precision, int variant);
+
+}  // namespace rlb

@@ -1,0 +1,552 @@
+// Kernels of the relativistic MRT lattice Boltzmann step for gfx950.
+//
+// Population storage (one buffer): 38 planes of cs elements, planes 0..18 hold
+// f_a and planes 19..37 hold g_a (velocity order of rlb.h); a cell's element
+// in every plane sits at the same index. Two such buffers alternate (A/B):
+// a step pulls from one and writes the other, so it is race-free.
+//
+// The fused step kernel reads 38 values per cell (streaming with periodic or
+// zero-gradient sources), collides in registers (cell.hpp) and writes 38
+// values: 2 x 38 x sizeof(T) bytes of HBM traffic per cell update, no reuse.
+// Loads use a uniform plane base plus a 32-bit byte offset per lane; stores
+// are nontemporal (written once, read by the next step from HBM).
+
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace rlb {
+
+namespace {
+
+__device__ __forceinline__ int nbr(int c, int d, int N, int bc) {
+  int s = c + d;
+  if (s < 0) s = bc ? 0 : N - 1;
+  if (s >= N) s = bc ? N - 1 : 0;
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* plane, uint32_t byteoff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + byteoff);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_nt(T* plane, uint32_t byteoff, T v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + byteoff));
+}
+
+template <typename T>
+__device__ __forceinline__ void st(T* plane, uint32_t byteoff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(plane) + byteoff) = v;
+}
+
+// Byte offsets of the 19 pull sources of cell (x, y, z) (source = cell - e_a).
+__device__ __forceinline__ void pull_offsets(int x, int y, int z, int nx, int ny, int nz, int bcx,
+                                             int bcy, int bcz, uint32_t base, uint32_t esz,
+                                             uint32_t (&off)[19], uint32_t& self) {
+  const int xm = nbr(x, -1, nx, bcx), xp = nbr(x, 1, nx, bcx);
+  const int ym = nbr(y, -1, ny, bcy), yp = nbr(y, 1, ny, bcy);
+  const int zm = nbr(z, -1, nz, bcz), zp = nbr(z, 1, nz, bcz);
+  const uint32_t unx = (uint32_t)nx, uny = (uint32_t)ny;
+  const uint32_t r_c = base + ((uint32_t)z * uny + (uint32_t)y) * unx;
+  const uint32_t r_ym = base + ((uint32_t)z * uny + (uint32_t)ym) * unx;
+  const uint32_t r_yp = base + ((uint32_t)z * uny + (uint32_t)yp) * unx;
+  const uint32_t r_zm = base + ((uint32_t)zm * uny + (uint32_t)y) * unx;
+  const uint32_t r_zp = base + ((uint32_t)zp * uny + (uint32_t)y) * unx;
+  const uint32_t r_ymzm = base + ((uint32_t)zm * uny + (uint32_t)ym) * unx;
+  const uint32_t r_ypzp = base + ((uint32_t)zp * uny + (uint32_t)yp) * unx;
+  const uint32_t r_ymzp = base + ((uint32_t)zp * uny + (uint32_t)ym) * unx;
+  const uint32_t r_ypzm = base + ((uint32_t)zm * uny + (uint32_t)yp) * unx;
+  const uint32_t X = (uint32_t)x, XM = (uint32_t)xm, XP = (uint32_t)xp;
+  off[0] = (r_c + X) * esz;
+  off[1] = (r_c + XM) * esz;
+  off[2] = (r_c + XP) * esz;
+  off[3] = (r_ym + X) * esz;
+  off[4] = (r_yp + X) * esz;
+  off[5] = (r_zm + X) * esz;
+  off[6] = (r_zp + X) * esz;
+  off[7] = (r_ym + XM) * esz;
+  off[8] = (r_yp + XP) * esz;
+  off[9] = (r_yp + XM) * esz;
+  off[10] = (r_ym + XP) * esz;
+  off[11] = (r_zm + XM) * esz;
+  off[12] = (r_zp + XP) * esz;
+  off[13] = (r_zp + XM) * esz;
+  off[14] = (r_zm + XP) * esz;
+  off[15] = (r_ymzm + X) * esz;
+  off[16] = (r_ypzp + X) * esz;
+  off[17] = (r_ymzp + X) * esz;
+  off[18] = (r_ypzm + X) * esz;
+  self = off[0];
+}
+
+// Sum five doubles over the block; the result is valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum5(double (&v)[5], int tid) {
+  __shared__ double sh[(NT + 63) / 64][5];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) v[i] += __shfl_xor(v[i], o, 64);
+  const int lane = tid & 63, wid = tid >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < 5; ++i) sh[wid][i] = v[i];
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      double s = 0.0;
+      for (int w = 0; w < (NT + 63) / 64; ++w) s += sh[w][i];
+      v[i] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// -------------------------------------------------------------------------
+// Fused step on one lattice: grid (ceil(nx/BX), ceil(ny/BY), ceil(nz/CZ)),
+// block (BX, BY); each thread updates CZ cells along z.
+// -------------------------------------------------------------------------
+template <typename T, int BX, int BY, int CZ, bool DIAG>
+__global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ src,
+                                                        T* __restrict__ dst, LatticeGeom geo,
+                                                        double* __restrict__ partials,
+                                                        unsigned long long* __restrict__ bad) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int y = blockIdx.y * BY + threadIdx.y;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const bool act = (x < geo.nx) && (y < geo.ny);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int nbad = 0;
+  const uint32_t esz = sizeof(T);
+#pragma unroll 1
+  for (int k = 0; k < CZ; ++k) {
+    const int z = blockIdx.z * CZ + k;
+    if (act && z < geo.nz) {
+      uint32_t off[19], self;
+      pull_offsets(x, y, z, geo.nx, geo.ny, geo.nz, geo.bcx, geo.bcy, geo.bcz, 0u, esz, off,
+                   self);
+      T f[19], g[19];
+#pragma unroll
+      for (int a = 0; a < 19; ++a) {
+        f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
+        g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
+      }
+      Sums s;
+      const bool ok = collide<T>(f, g, geo.rt, geo.ref, s);
+      nbad += ok ? 0 : 1;
+      if (DIAG)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+      for (int a = 0; a < 19; ++a) {
+        st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+        st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+      }
+    }
+  }
+  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (DIAG) {
+    block_sum5<BX * BY>(acc, tid);
+    if (tid == 0) {
+      const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) partials[b * 5 + i] = acc[i];
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// Persistent step over a batch: one block per member, all nsteps inside the
+// launch with a block barrier between steps (members are independent, so no
+// grid-wide synchronisation exists). Each thread updates CPT cells per sweep,
+// interleaved by NT so every load instruction is coalesced.
+// -------------------------------------------------------------------------
+template <typename T, int NT, int CPT>
+__global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
+  const MemberDesc d = a.descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const uint32_t esz = sizeof(T);
+  const uint32_t base = (uint32_t)d.offset;
+  int nbad = 0;
+  for (int t = 0; t < a.nsteps; ++t) {
+    const bool odd = a.pingpong && (t & 1);
+    const T* __restrict__ src = (const T*)(odd ? a.bufB : a.bufA);
+    T* __restrict__ dst = (T*)(odd ? a.bufA : a.bufB);
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag = a.diag_every > 0 && ((sidx % a.diag_every) == 0 || t == a.nsteps - 1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < d.ncells; c0 += NT * CPT) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int c = c0 + k * NT + tid;
+        if (c < d.ncells) {
+          const int x = c % d.nx;
+          const int yz = c / d.nx;
+          const int y = yz % d.ny;
+          const int z = yz / d.ny;
+          uint32_t off[19], self;
+          pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, base, esz, off, self);
+          T f[19], g[19];
+#pragma unroll
+          for (int q = 0; q < 19; ++q) {
+            f[q] = ld(src + (int64_t)q * a.cs, off[q]);
+            g[q] = ld(src + (int64_t)(19 + q) * a.cs, off[q]);
+          }
+          Sums s;
+          const bool ok = collide<T>(f, g, d.rt, d.ref, s);
+          nbad += ok ? 0 : 1;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+          for (int q = 0; q < 19; ++q) {
+            st(dst + (int64_t)q * a.cs, self, f[q]);
+            st(dst + (int64_t)(19 + q) * a.cs, self, g[q]);
+          }
+        }
+      }
+    }
+    if (diag) {
+      block_sum5<NT>(acc, tid);
+      if (tid == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
+    }
+    __syncthreads();
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
+__device__ __forceinline__ int find_member(const MemberDesc* __restrict__ d, int n, int64_t c) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].offset <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Mean n gamma and eps/3 of each member's initial fields (its reference
+// state), in two deterministic passes: kRefBlocks partial sums per member,
+// then one block per member adds them in order.
+__global__ __launch_bounds__(256) void k_member_ref_parts(const MemberDesc* descs,
+                                                          const double* n0, const double* eps0,
+                                                          const double* u0, int64_t ncells,
+                                                          double* parts) {
+  const MemberDesc& d = descs[blockIdx.y];
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += kRefBlocks * 256) {
+    const int64_t i = d.offset + c;
+    const double ux = u0[i], uy = u0[ncells + i], uz = u0[2 * ncells + i];
+    v[0] += n0[i] / sqrt(1.0 - (ux * ux + uy * uy + uz * uz));
+    v[1] += eps0[i];
+  }
+  block_sum5<256>(v, threadIdx.x);
+  if (threadIdx.x == 0) {
+    const int64_t b = (int64_t)blockIdx.y * kRefBlocks + blockIdx.x;
+    for (int k = 0; k < 5; ++k) parts[b * 5 + k] = v[k];
+  }
+}
+
+__global__ __launch_bounds__(64) void k_member_ref_final(MemberDesc* descs, const double* parts) {
+  if (threadIdx.x != 0) return;
+  MemberDesc& d = descs[blockIdx.x];
+  double sn = 0.0, se = 0.0;
+  for (int b = 0; b < kRefBlocks; ++b) {
+    sn += parts[((int64_t)blockIdx.x * kRefBlocks + b) * 5 + 0];
+    se += parts[((int64_t)blockIdx.x * kRefBlocks + b) * 5 + 1];
+  }
+  d.ref.n = sn / d.ncells;
+  d.ref.P = se / (3.0 * d.ncells);
+}
+
+__global__ __launch_bounds__(256) void k_validate(const double* n0, const double* eps0,
+                                                  const double* u0, int64_t ncells,
+                                                  unsigned long long* count) {
+  int nb = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const double ux = u0[i], uy = u0[ncells + i], uz = u0[2 * ncells + i];
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const bool ok = (eps0[i] > 0.0) && (n0[i] >= 0.0) && (uu < 1.0) && (n0[i] < INFINITY) &&
+                    (eps0[i] < INFINITY);
+    nb += ok ? 0 : 1;
+  }
+  if (nb) atomicAdd(count, (unsigned long long)nb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(T* state, int64_t cs, const MemberDesc* descs,
+                                              int n_members, const double* n0,
+                                              const double* eps0, const double* u0,
+                                              int64_t ncells) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[find_member(descs, n_members, i)].ref;
+    double f[19], g[19];
+    equilibrium_dev(n0[i], eps0[i], u0[i], u0[ncells + i], u0[2 * ncells + i], ref, f, g);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      state[a * cs + i] = (T)f[a];
+      state[(19 + a) * cs + i] = (T)g[a];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_export(const T* state, int64_t cs,
+                                                const MemberDesc* descs, int n_members,
+                                                int64_t ncells, double* n, double* eps,
+                                                double* P, double* gamma, double* u,
+                                                double* partials) {
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[find_member(descs, n_members, i)].ref;
+    T f[19], g[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) {
+      f[a] = state[a * cs + i];
+      g[a] = state[(19 + a) * cs + i];
+    }
+    double N, E, Mx, My, Mz, fs, gs;
+    cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
+    acc[0] += N;
+    acc[1] += E;
+    acc[2] += Mx;
+    acc[3] += My;
+    acc[4] += Mz;
+    Macro m;
+    const bool ok = recover(E, Mx, My, Mz, m);
+    const double nan = __builtin_nan("");
+    const double e = ok ? 0.75 * m.sigma * (1.0 - m.u2) : nan;
+    const double gm = ok ? 1.0 / sqrt(1.0 - m.u2) : nan;
+    if (n) n[i] = ok ? N / gm : nan;
+    if (eps) eps[i] = e;
+    if (P) P[i] = ok ? e / 3.0 : nan;
+    if (gamma) gamma[i] = gm;
+    if (u) {
+      u[i] = ok ? m.ux : nan;
+      u[ncells + i] = ok ? m.uy : nan;
+      u[2 * ncells + i] = ok ? m.uz : nan;
+    }
+  }
+  block_sum5<256>(acc, threadIdx.x);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) partials[(int64_t)blockIdx.x * 5 + k] = acc[k];
+}
+
+// Planes [p0, p0 + np) of the state as FP64 populations (reference added back);
+// plane p < 19 is f_p, plane p >= 19 is g_(p-19). out[(p - p0) * ncells + cell].
+template <typename T>
+__global__ __launch_bounds__(256) void k_population_planes(const T* state, int64_t cs,
+                                                           const MemberDesc* descs, int n_members,
+                                                           int64_t ncells, int p0, int np,
+                                                           double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[find_member(descs, n_members, i)].ref;
+    for (int p = p0; p < p0 + np; ++p) {
+      const double r = p < 19 ? weight(p) * ref.n : gref_unit(p - 19) * ref.P;
+      out[(int64_t)(p - p0) * ncells + i] = (double)state[p * cs + i] + r;
+    }
+  }
+}
+
+// Deterministic sum of nparts partial 5-vectors (single block).
+__global__ __launch_bounds__(256) void k_reduce(const double* partials, int nparts, double* out) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < nparts; j += 256)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] += partials[(int64_t)j * 5 + k];
+  block_sum5<256>(v, threadIdx.x);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) out[k] = v[k];
+}
+
+// ------------------------------ variants ---------------------------------
+constexpr LatticeVariant kLat[] = {{64, 1, 1}, {64, 4, 1}, {128, 2, 1}, {256, 1, 1},
+                                   {64, 4, 2}, {256, 1, 2}, {128, 2, 4}, {256, 1, 4}};
+constexpr int kNumLat = sizeof(kLat) / sizeof(kLat[0]);
+constexpr MemberVariant kMem[] = {{256, 1}, {512, 1}, {1024, 1}, {256, 2}, {512, 2}, {1024, 2}};
+constexpr int kNumMem = sizeof(kMem) / sizeof(kMem[0]);
+
+int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T, int BX, int BY, int CZ>
+hipError_t lat_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
+                      double* partials, unsigned long long* bad, hipStream_t s) {
+  dim3 block(BX, BY, 1);
+  dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + CZ - 1) / CZ);
+  if (diag)
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true>), grid, block, 0, s, (const T*)src,
+                       (T*)dst, g, partials, bad);
+  else
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lat_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
+                        double* partials, unsigned long long* bad, hipStream_t s) {
+  switch (v) {
+    case 0: return lat_launch<T, 64, 1, 1>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat_launch<T, 64, 4, 1>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat_launch<T, 128, 2, 1>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat_launch<T, 256, 1, 1>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat_launch<T, 64, 4, 2>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat_launch<T, 256, 1, 2>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat_launch<T, 128, 2, 4>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat_launch<T, 256, 1, 4>(diag, src, dst, g, partials, bad, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+const void* mem_func(int v) {
+  switch (v) {
+    case 0: return (const void*)&k_step_members<T, 256, 1>;
+    case 1: return (const void*)&k_step_members<T, 512, 1>;
+    case 2: return (const void*)&k_step_members<T, 1024, 1>;
+    case 3: return (const void*)&k_step_members<T, 256, 2>;
+    case 4: return (const void*)&k_step_members<T, 512, 2>;
+    case 5: return (const void*)&k_step_members<T, 1024, 2>;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+int num_lattice_variants() { return kNumLat; }
+LatticeVariant lattice_variant(int i) { return kLat[i]; }
+int num_member_variants() { return kNumMem; }
+MemberVariant member_variant(int i) { return kMem[i]; }
+
+int lattice_partials(int v, const LatticeGeom& g) {
+  const LatticeVariant lv = kLat[v];
+  return ((g.nx + lv.bx - 1) / lv.bx) * ((g.ny + lv.by - 1) / lv.by) *
+         ((g.nz + lv.cz - 1) / lv.cz);
+}
+
+const char* lattice_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_step_lattice<float,64,1,1>",  "k_step_lattice<float,64,4,1>",
+                              "k_step_lattice<float,128,2,1>", "k_step_lattice<float,256,1,1>",
+                              "k_step_lattice<float,64,4,2>",  "k_step_lattice<float,256,1,2>",
+                              "k_step_lattice<float,128,2,4>", "k_step_lattice<float,256,1,4>"};
+  static const char* n64[] = {
+      "k_step_lattice<double,64,1,1>",  "k_step_lattice<double,64,4,1>",
+      "k_step_lattice<double,128,2,1>", "k_step_lattice<double,256,1,1>",
+      "k_step_lattice<double,64,4,2>",  "k_step_lattice<double,256,1,2>",
+      "k_step_lattice<double,128,2,4>", "k_step_lattice<double,256,1,4>"};
+  if (v < 0 || v >= kNumLat) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+const char* member_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_step_members<float,256,1>",  "k_step_members<float,512,1>",
+                              "k_step_members<float,1024,1>", "k_step_members<float,256,2>",
+                              "k_step_members<float,512,2>",  "k_step_members<float,1024,2>"};
+  static const char* n64[] = {"k_step_members<double,256,1>",  "k_step_members<double,512,1>",
+                              "k_step_members<double,1024,1>", "k_step_members<double,256,2>",
+                              "k_step_members<double,512,2>",  "k_step_members<double,1024,2>"};
+  if (v < 0 || v >= kNumMem) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const double* n0,
+                              const double* eps0, const double* u0, int64_t ncells,
+                              double* parts, hipStream_t s) {
+  hipLaunchKernelGGL(k_member_ref_parts, dim3(kRefBlocks, n_members), dim3(256), 0, s, descs, n0,
+                     eps0, u0, ncells, parts);
+  hipLaunchKernelGGL(k_member_ref_final, dim3(n_members), dim3(64), 0, s,
+                     const_cast<MemberDesc*>(descs), (const double*)parts);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
+                           int64_t ncells, unsigned long long* count, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(grid_for(ncells)), dim3(256), 0, s, n0, eps0, u0, ncells,
+                     count);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
+                       int n_members, const double* n0, const double* eps0, const double* u0,
+                       int64_t ncells, hipStream_t s) {
+  dim3 grid(grid_for(ncells));
+  if (precision)
+    hipLaunchKernelGGL(k_init<float>, grid, dim3(256), 0, s, (float*)state, cs, descs,
+                       n_members, n0, eps0, u0, ncells);
+  else
+    hipLaunchKernelGGL(k_init<double>, grid, dim3(256), 0, s, (double*)state, cs, descs,
+                       n_members, n0, eps0, u0, ncells);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_lattice(int precision, int v, bool diag, const void* src, void* dst,
+                               const LatticeGeom& g, double* partials,
+                               unsigned long long* bad, hipStream_t s) {
+  if (precision) return lat_dispatch<float>(v, diag, src, dst, g, partials, bad, s);
+  return lat_dispatch<double>(v, diag, src, dst, g, partials, bad, s);
+}
+
+hipError_t member_kernel(int precision, int v, const void** func, dim3* block) {
+  if (v < 0 || v >= kNumMem) return hipErrorInvalidValue;
+  *func = precision ? mem_func<float>(v) : mem_func<double>(v);
+  *block = dim3(kMem[v].nt, 1, 1);
+  return hipSuccess;
+}
+
+hipError_t launch_step_members(int precision, int v, int n_members, const MemberLaunch& a,
+                               hipStream_t s) {
+  const void* f;
+  dim3 block;
+  hipError_t e = member_kernel(precision, v, &f, &block);
+  if (e != hipSuccess) return e;
+  void* args[] = {const_cast<MemberLaunch*>(&a)};
+  return hipLaunchKernel(f, dim3(n_members), block, args, 0, s);
+}
+
+hipError_t launch_export(int precision, const void* state, int64_t cs, const MemberDesc* descs,
+                         int n_members, int64_t ncells, double* n, double* eps, double* P,
+                         double* gamma, double* u, double* partials, int nparts,
+                         hipStream_t s) {
+  if (precision)
+    hipLaunchKernelGGL(k_export<float>, dim3(nparts), dim3(256), 0, s, (const float*)state, cs,
+                       descs, n_members, ncells, n, eps, P, gamma, u, partials);
+  else
+    hipLaunchKernelGGL(k_export<double>, dim3(nparts), dim3(256), 0, s, (const double*)state,
+                       cs, descs, n_members, ncells, n, eps, P, gamma, u, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_population_planes(int precision, const void* state, int64_t cs,
+                                    const MemberDesc* descs, int n_members, int64_t ncells,
+                                    int p0, int np, double* out, hipStream_t s) {
+  dim3 grid(grid_for(ncells));
+  if (precision)
+    hipLaunchKernelGGL(k_population_planes<float>, grid, dim3(256), 0, s, (const float*)state,
+                       cs, descs, n_members, ncells, p0, np, out);
+  else
+    hipLaunchKernelGGL(k_population_planes<double>, grid, dim3(256), 0, s,
+                       (const double*)state, cs, descs, n_members, ncells, p0, np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nparts, double* out5, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, out5);
+  return hipGetLastError();
+}
+
+}  // namespace rlb
