@@ -1,13 +1,257 @@
 // Tape and adjoint of the g update (rlb_grad).
+//
+// Forward: rlb_step keeps g every K steps (checkpoints). Reverse: for each
+// segment [kK, kK + K), last first, the g states are recomputed from the
+// checkpoint with a g-only step that is bit-identical to the forward (g never
+// reads f), then one adjoint kernel per step runs backwards. Each adjoint
+// kernel reads, per cell, the 19 forward populations it pulled at that step
+// (from the recomputed state), gathers the 19 adjoint populations of the cells
+// that pulled from it (the transpose of streaming: one source per population
+// in the interior, up to four at clamped corners, never an atomic), applies
+// the transposed collision Jacobian (adjoint_cell.hpp) and writes 19 values:
+// 3 x 19 populations of traffic per cell-step. dL/dtau is accumulated in FP64
+// per block across all steps and reduced once at the end.
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "adjoint.hpp"
+#include "adjoint_cell.hpp"
+#include "device_util.hpp"
 
 namespace rlb {
 
 namespace {
+
 size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+int grid_of(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+__device__ __forceinline__ void decompose(int c, const MemberDesc& d, int& x, int& y, int& z) {
+  x = c % d.nx;
+  const int yz = c / d.nx;
+  y = yz % d.ny;
+  z = yz / d.ny;
+}
+
+// Cells y with src(y, e) = c along one axis (the pull source is y - e,
+// wrapped or clamped): one in the interior, up to two at a clamped end.
+__device__ __forceinline__ int preimages(int c, int e, int N, int bc, int (&out)[2]) {
+  if (e == 0) {
+    out[0] = c;
+    return 1;
+  }
+  int s = c + e;
+  if (bc == 0) {
+    if (s < 0) s += N;
+    if (s >= N) s -= N;
+    out[0] = s;
+    return 1;
+  }
+  int n = 0;
+  if (s >= 0 && s <= N - 1) out[n++] = s;
+  if (e > 0 && c == 0) out[n++] = 0;
+  if (e < 0 && c == N - 1) out[n++] = N - 1;
+  return n;
+}
+
+// Transposed streaming: adjoint of the pre-collision populations of the cells
+// that pulled population a from cell (x, y, z), summed.
+template <typename T>
+__device__ __forceinline__ void gather_adjoint(const T* __restrict__ adj, int64_t cs, int x, int y,
+                                               int z, const MemberDesc& d, T (&gb)[19]) {
+#pragma unroll
+  for (int a = 0; a < 19; ++a) {
+    int px[2], py[2], pz[2];
+    const int nxp = preimages(x, ex(a), d.nx, d.bcx, px);
+    const int nyp = preimages(y, ey(a), d.ny, d.bcy, py);
+    const int nzp = preimages(z, ez(a), d.nz, d.bcz, pz);
+    T s = T(0.0);
+    for (int k = 0; k < nzp; ++k)
+      for (int j = 0; j < nyp; ++j)
+        for (int i = 0; i < nxp; ++i)
+          s += adj[(int64_t)a * cs + ((int64_t)pz[k] * d.ny + py[j]) * d.nx + px[i]];
+    gb[a] = s;
+  }
+}
+
+// g-only forward step between g-plane buffers (recomputation of a segment).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gstep(const T* __restrict__ src, T* __restrict__ dst,
+                                               int64_t cs, MemberDesc d) {
+  const uint32_t esz = sizeof(T);
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
+    int x, y, z;
+    decompose(c, d, x, y, z);
+    uint32_t off[19], self;
+    pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self);
+    T g[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) g[a] = ld(src + (int64_t)a * cs, off[a]);
+    collide_g_only(g, d.rt, d.ref);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) st(dst + (int64_t)a * cs, self, g[a]);
+  }
+}
+
+// dL/dg* of the final state from dL/du, dL/deps.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_loss(const T* __restrict__ state, int64_t cs,
+                                                  MemberDesc d, const double* __restrict__ dLdu,
+                                                  const double* __restrict__ dLdeps,
+                                                  T* __restrict__ out) {
+  const int64_t nc = d.ncells;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
+    T g[19], gb[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) g[a] = state[(int64_t)a * cs + c];
+    loss_adjoint(g, d.ref, dLdu[c], dLdu[nc + c], dLdu[2 * nc + c], dLdeps[c], gb);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) out[(int64_t)a * cs + c] = gb[a];
+  }
+}
+
+// One reverse step. state: g*(t) (the step's input); adj_in: either the
+// adjoint of g*(t+1) (GATHER = false, straight from the loss) or the
+// pre-collision adjoint of step t+1 (GATHER = true, transposed streaming
+// applied here). adj_out: pre-collision adjoint of step t.
+template <typename T, bool GATHER>
+__global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
+                                                  const T* __restrict__ adj_in,
+                                                  T* __restrict__ adj_out, int64_t cs,
+                                                  MemberDesc d, double* __restrict__ partials) {
+  const uint32_t esz = sizeof(T);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
+    int x, y, z;
+    decompose(c, d, x, y, z);
+    uint32_t off[19], self;
+    pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self);
+    T g[19], gb[19];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) g[a] = ld(state + (int64_t)a * cs, off[a]);
+    if (GATHER) {
+      gather_adjoint(adj_in, cs, x, y, z, d, gb);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 19; ++a) gb[a] = adj_in[(int64_t)a * cs + c];
+    }
+    double dt[4] = {0.0, 0.0, 0.0, 0.0};
+    cell_adjoint(g, gb, d.rt, d.ref, dt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] += dt[k];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self, gb[a]);
+  }
+  block_sum5<256>(acc, threadIdx.x);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) partials[(int64_t)blockIdx.x * 5 + k] += acc[k];
+}
+
+// dL/deps0, dL/du0 from the adjoint of the initial state.
+template <typename T, bool GATHER>
+__global__ __launch_bounds__(256) void k_adj_init(const T* __restrict__ adj_in, int64_t cs,
+                                                  MemberDesc d, const double* __restrict__ f0,
+                                                  double* __restrict__ deps0,
+                                                  double* __restrict__ du0) {
+  const int64_t nc = d.ncells;
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
+    T gb[19];
+    if (GATHER) {
+      int x, y, z;
+      decompose(c, d, x, y, z);
+      gather_adjoint(adj_in, cs, x, y, z, d, gb);
+    } else {
+#pragma unroll
+      for (int a = 0; a < 19; ++a) gb[a] = adj_in[(int64_t)a * cs + c];
+    }
+    double de, dx, dy, dz;
+    init_adjoint(gb, f0[c], f0[nc + c], f0[2 * nc + c], f0[3 * nc + c], de, dx, dy, dz);
+    deps0[c] = de;
+    du0[c] = dx;
+    du0[nc + c] = dy;
+    du0[2 * nc + c] = dz;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int n, double* out) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = threadIdx.x; j < n; j += 256)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] += parts[(int64_t)j * 5 + k];
+  block_sum5<256>(v, threadIdx.x);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) out[k] = v[k];
+}
+
+template <typename T>
+rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const double* dLdeps,
+                    double dL_dtau[3], double* deps0, double* du0) {
+  const TapeLayout& L = t.L;
+  const MemberDesc d = c.desc;
+  const int64_t cs = c.cs;
+  const int64_t T_steps = c.steps;
+  const int K = L.K;
+  hipStream_t s = c.stream;
+  const dim3 grid(grid_of(c.ncells)), block(256);
+  auto ckpt = [&](int64_t k) { return (T*)(t.base + L.off_ckpt + (size_t)k * L.gbytes); };
+  auto seg = [&](int64_t j) { return (T*)(t.base + L.off_seg + (size_t)j * L.gbytes); };
+  T* adj[2] = {(T*)(t.base + L.off_adj), (T*)(t.base + L.off_adj + L.gbytes)};
+  const double* f0 = (const double*)(t.base + L.off_fields);
+  double* parts = (double*)(t.base + L.off_tparts);
+  if (hipMemsetAsync(parts, 0, sizeof(double) * 5 * (size_t)grid.x, s) != hipSuccess)
+    return RLB_E_DEVICE;
+  const T* final_g = (const T*)((const char*)c.state + 19 * (size_t)cs * sizeof(T));
+  hipLaunchKernelGGL(k_adj_loss<T>, grid, block, 0, s, final_g, cs, d, dLdu, dLdeps, adj[0]);
+  int cur = 0;
+  bool gathered = false;
+  if (T_steps > 0) {
+    for (int64_t k = (T_steps - 1) / K; k >= 0; --k) {
+      const int64_t t0 = k * K;
+      const int64_t t1 = std::min<int64_t>(t0 + K, T_steps);
+      const T* prev = ckpt(k);
+      for (int64_t tt = t0 + 1; tt < t1; ++tt) {
+        hipLaunchKernelGGL(k_gstep<T>, grid, block, 0, s, prev, seg(tt - t0), cs, d);
+        prev = seg(tt - t0);
+      }
+      for (int64_t tt = t1 - 1; tt >= t0; --tt) {
+        const T* st = (tt == t0) ? ckpt(k) : seg(tt - t0);
+        if (gathered)
+          hipLaunchKernelGGL((k_adj_step<T, true>), grid, block, 0, s, st, adj[cur],
+                             adj[1 - cur], cs, d, parts);
+        else
+          hipLaunchKernelGGL((k_adj_step<T, false>), grid, block, 0, s, st, adj[cur],
+                             adj[1 - cur], cs, d, parts);
+        cur = 1 - cur;
+        gathered = true;
+      }
+    }
+  }
+  if (gathered)
+    hipLaunchKernelGGL((k_adj_init<T, true>), grid, block, 0, s, adj[cur], cs, d, f0, deps0, du0);
+  else
+    hipLaunchKernelGGL((k_adj_init<T, false>), grid, block, 0, s, adj[cur], cs, d, f0, deps0,
+                       du0);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, parts, (int)grid.x, c.sums_out);
+  if (hipGetLastError() != hipSuccess) return RLB_E_DEVICE;
+  double h[5];
+  if (hipMemcpyAsync(h, c.sums_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return RLB_E_DEVICE;
+  // groups: v, e, eps, q (q folds into v when the ghost rows follow tau_v)
+  dL_dtau[0] = h[0] + (c.tau_q_tied ? h[3] : 0.0);
+  dL_dtau[1] = h[1];
+  dL_dtau[2] = h[2];
+  return RLB_OK;
+}
+
 }  // namespace
 
 TapeLayout tape_layout(int64_t ncells, int64_t cs, size_t esz, int K, int tape_steps,
@@ -63,15 +307,34 @@ rlb_status tape_checkpoint(Tape& t, int64_t idx, const void* state, hipStream_t 
 
 rlb_status tape_grad(Tape& t, const GradContext& c, const double* dL_du, const double* dL_deps,
                      double dL_dtau[3], double* dL_deps0, double* dL_du0, int io_on_device) {
-  (void)t;
-  (void)c;
-  (void)dL_du;
-  (void)dL_deps;
-  (void)dL_dtau;
-  (void)dL_deps0;
-  (void)dL_du0;
-  (void)io_on_device;
-  return RLB_E_UNSUPPORTED;
+  if (!t.base) return RLB_E_STATE;
+  const int64_t nc = c.ncells;
+  const double *du = dL_du, *de = dL_deps;
+  double *oe = dL_deps0, *ou = dL_du0;
+  if (!io_on_device) {
+    double* st = c.stage;
+    if (hipMemcpyAsync(st, dL_du, sizeof(double) * 3 * nc, hipMemcpyHostToDevice, c.stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(st + 3 * nc, dL_deps, sizeof(double) * nc, hipMemcpyHostToDevice,
+                       c.stream) != hipSuccess)
+      return RLB_E_DEVICE;
+    du = st;
+    de = st + 3 * nc;
+    oe = st + 4 * nc;
+    ou = st + 5 * nc;
+  }
+  rlb_status r = c.precision ? run_grad<float>(t, c, du, de, dL_dtau, oe, ou)
+                             : run_grad<double>(t, c, du, de, dL_dtau, oe, ou);
+  if (r != RLB_OK) return r;
+  if (!io_on_device) {
+    if (hipMemcpyAsync(dL_deps0, oe, sizeof(double) * nc, hipMemcpyDeviceToHost, c.stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(dL_du0, ou, sizeof(double) * 3 * nc, hipMemcpyDeviceToHost, c.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c.stream) != hipSuccess)
+      return RLB_E_DEVICE;
+  }
+  return RLB_OK;
 }
 
 void tape_release(Tape& t) { t.base = nullptr; }

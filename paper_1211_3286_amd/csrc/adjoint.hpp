@@ -42,12 +42,12 @@ rlb_status tape_checkpoint(Tape& t, int64_t idx, const void* state, hipStream_t 
 struct GradContext {
   int precision;
   int64_t ncells, cs;
-  MemberDesc desc;
-  int64_t steps;
-  bool lattice;
-  int variant;
-  const MemberDesc* d_descs;
-  double* stage;  // 8 * ncells doubles of staging
+  MemberDesc desc;        // geometry, rates and reference of the (single) lattice
+  int64_t steps;          // forward steps taken since rlb_init
+  bool tau_q_tied;        // ghost rows relax with tau_v
+  const void* state;      // current population buffer (38 planes)
+  double* stage;          // 8 * ncells doubles of staging
+  double* sums_out;       // 5 doubles of device scratch
   hipStream_t stream;
 };
 

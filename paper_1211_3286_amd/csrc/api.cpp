@@ -570,10 +570,10 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
   c.cs = h->L.cs;
   c.desc = h->descs[0];
   c.steps = h->steps;
-  c.lattice = h->lattice;
-  c.variant = h->variant;
-  c.d_descs = h->d_descs;
+  c.tau_q_tied = !(h->params[0].tau_q > 0.0);
+  c.state = state_buf(h);
   c.stage = h->d_stage;
+  c.sums_out = h->d_small;
   c.stream = h->stream;
   return rlb::tape_grad(h->tape, c, dL_du, dL_deps, dL_dtau, dL_deps0, dL_du0, io_on_device);
 }

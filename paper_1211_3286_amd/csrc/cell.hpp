@@ -4,9 +4,9 @@
 // from a rest reference state (n_r, P_r) of the member:
 //   f_a = w_a n_r + f~_a,   g_a = gref_a + g~_a,
 //   gref = (P_r, P_r/6 on the faces, P_r/12 on the edges) = g_eq(3 P_r, P_r, 0).
-// Storing the deviation keeps FP32 rounding relative to the (small) departure
-// from the reference instead of to the full population; it costs one add per
-// reference moment and nothing per population.
+// Storing the deviation keeps FP32 rounding relative to the departure from the
+// reference instead of to the full population; it costs one add per reference
+// moment and nothing per population.
 //
 // Per cell (Sec. II and Sec. V.A of the paper):
 //   1. Eq. (10) sums in FP64: N = sum f (= n gamma), E = sum g (= sigma - P),
@@ -72,16 +72,15 @@ __host__ __device__ constexpr double gref_unit(int a) {
   return a == 0 ? 1.0 : (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0);
 }
 
-// FP64 Eq. (10) sums of a cell from its stored deviations. fs and gs are the
-// plain sums of the stored f and g values (N = n_r + fs, E = 3 P_r + gs).
+// Squared norms of the basis rows (sum over the velocities of row^2).
+constexpr double kNormE = 2394.0, kNormEps = 252.0, kNormQ = 40.0, kNorm3P = 36.0,
+                 kNorm3Pi = 72.0, kNormW = 12.0, kNormWPi = 24.0, kNormPxy = 4.0, kNormM = 8.0;
+
+// FP64 sums of the stored g values: gs = sum g~, E = 3 P_r + gs, M = sum e g~
+// (the reference has no momentum).
 template <typename C>
-__device__ __forceinline__ void cell_sums(const C (&f)[19], const C (&g)[19], const Ref& ref,
-                                          double& N, double& E, double& Mx, double& My,
-                                          double& Mz, double& fs, double& gs) {
-  fs = 0.0;
-#pragma unroll
-  for (int a = 0; a < 19; ++a) fs += (double)f[a];
-  N = ref.n + fs;
+__device__ __forceinline__ void g_sums(const C (&g)[19], const Ref& ref, double& E, double& Mx,
+                                       double& My, double& Mz, double& gs) {
   double gd[19];
 #pragma unroll
   for (int a = 0; a < 19; ++a) gd[a] = (double)g[a];
@@ -97,6 +96,19 @@ __device__ __forceinline__ void cell_sums(const C (&f)[19], const C (&g)[19], co
   Mx = D1 + (D7 + D9) + (D11 + D13);
   My = D3 + (D7 - D9) + (D15 + D17);
   Mz = D5 + (D11 - D13) + (D15 - D17);
+}
+
+// FP64 Eq. (10) sums of a cell from its stored deviations. fs and gs are the
+// plain sums of the stored f and g values (N = n_r + fs, E = 3 P_r + gs).
+template <typename C>
+__device__ __forceinline__ void cell_sums(const C (&f)[19], const C (&g)[19], const Ref& ref,
+                                          double& N, double& E, double& Mx, double& My,
+                                          double& Mz, double& fs, double& gs) {
+  fs = 0.0;
+#pragma unroll
+  for (int a = 0; a < 19; ++a) fs += (double)f[a];
+  N = ref.n + fs;
+  g_sums(g, ref, E, Mx, My, Mz, gs);
 }
 
 // Recovery (FP64). Returns false for an inadmissible cell.
@@ -119,165 +131,214 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
   return ok;
 }
 
-// One collision in place on the stored deviations. Returns admissibility.
-// sums receives the FP64 Eq. (10) sums of the incoming populations.
+// The 15 non-conserved moments of a population vector.
 template <typename C>
-__device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt, const Ref& ref,
-                                        Sums& sums) {
-  double N, E, Mx, My, Mz, fs, gs;
-  cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
-  sums.v[0] = N;
-  sums.v[1] = E;
-  sums.v[2] = Mx;
-  sums.v[3] = My;
-  sums.v[4] = Mz;
-  Macro mac;
-  const bool ok = recover(E, Mx, My, Mz, mac);
-  if (!ok) return false;
+struct NonConserved {
+  C e, eps, qx, qy, qz, p3xx, pi3xx, pww, piww, pxy, pyz, pxz, mx, my, mz;
+};
 
-  // ---------------- f: BGK (Eq. 5), f_eq of Eq. (7) ----------------
-  {
-    const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)mac.u2;
-    const C Nc = (C)N;
-    const C b = (C)(N - ref.n) - C(1.5) * Nc * uu;  // deviation part of w-bracket
-    const C a3 = C(3.0) * Nc, a45 = C(4.5) * Nc;
-    const C wf = (C)rt.w_f;
-    const C w0 = C(1.0 / 3.0), w1 = C(1.0 / 18.0), w2 = C(1.0 / 36.0);
-    C eu[19];
-    eu[0] = C(0.0);
-    eu[1] = ux;
-    eu[2] = -ux;
-    eu[3] = uy;
-    eu[4] = -uy;
-    eu[5] = uz;
-    eu[6] = -uz;
-    eu[7] = ux + uy;
-    eu[8] = -(ux + uy);
-    eu[9] = ux - uy;
-    eu[10] = -(ux - uy);
-    eu[11] = ux + uz;
-    eu[12] = -(ux + uz);
-    eu[13] = ux - uz;
-    eu[14] = -(ux - uz);
-    eu[15] = uy + uz;
-    eu[16] = -(uy + uz);
-    eu[17] = uy - uz;
-    eu[18] = -(uy - uz);
+// m = M g on the non-conserved rows, from pair sums and differences.
+template <typename C>
+__device__ __forceinline__ NonConserved<C> moments_nc(const C (&g)[19]) {
+  const C g0 = g[0];
+  const C S1 = g[1] + g[2], S3 = g[3] + g[4], S5 = g[5] + g[6];
+  const C S7 = g[7] + g[8], S9 = g[9] + g[10], S11 = g[11] + g[12];
+  const C S13 = g[13] + g[14], S15 = g[15] + g[16], S17 = g[17] + g[18];
+  const C D1 = g[1] - g[2], D3 = g[3] - g[4], D5 = g[5] - g[6];
+  const C D7 = g[7] - g[8], D9 = g[9] - g[10], D11 = g[11] - g[12];
+  const C D13 = g[13] - g[14], D15 = g[15] - g[16], D17 = g[17] - g[18];
+  const C Sf = S1 + S3 + S5;
+  const C Exy = S7 + S9, Exz = S11 + S13, Eyz = S15 + S17;
+  const C Se = Exy + Exz + Eyz;
+  const C xyz_p = Exy + Exz - C(2.0) * Eyz;
+  NonConserved<C> m;
+  m.e = C(-30.0) * g0 - C(11.0) * Sf + C(8.0) * Se;
+  m.eps = C(12.0) * g0 - C(4.0) * Sf + Se;
+  m.p3xx = C(2.0) * S1 - S3 - S5 + xyz_p;
+  m.pi3xx = C(-4.0) * S1 + C(2.0) * S3 + C(2.0) * S5 + xyz_p;
+  m.pww = S3 - S5 + Exy - Exz;
+  m.piww = C(-2.0) * S3 + C(2.0) * S5 + Exy - Exz;
+  m.pxy = S7 - S9;
+  m.pxz = S11 - S13;
+  m.pyz = S15 - S17;
+  m.qx = C(-4.0) * D1 + D7 + D9 + D11 + D13;
+  m.qy = C(-4.0) * D3 + D7 - D9 + D15 + D17;
+  m.qz = C(-4.0) * D5 + D11 - D13 + D15 - D17;
+  m.mx = D7 + D9 - D11 - D13;
+  m.my = -D7 + D9 + D15 + D17;
+  m.mz = D11 - D13 - D15 + D17;
+  return m;
+}
+
+// g <- g - M^T c for a moment-space vector c (non-conserved rows only).
+template <typename C>
+__device__ __forceinline__ void sub_MT(C (&g)[19], const NonConserved<C>& c) {
+  const C face = C(-11.0) * c.e - C(4.0) * c.eps;
+  const C ev_x = face + C(2.0) * c.p3xx - C(4.0) * c.pi3xx;
+  const C ev_y = face - c.p3xx + C(2.0) * c.pi3xx + c.pww - C(2.0) * c.piww;
+  const C ev_z = face - c.p3xx + C(2.0) * c.pi3xx - c.pww + C(2.0) * c.piww;
+  const C edge = C(8.0) * c.e + c.eps;
+  const C ev_xy = edge + c.p3xx + c.pi3xx + c.pww + c.piww;
+  const C ev_xz = edge + c.p3xx + c.pi3xx - c.pww - c.piww;
+  const C ev_yz = edge - C(2.0) * (c.p3xx + c.pi3xx);
+  const C od_x = C(-4.0) * c.qx, od_y = C(-4.0) * c.qy, od_z = C(-4.0) * c.qz;
+  const C o7 = c.qx + c.qy + c.mx - c.my;
+  const C o9 = c.qx - c.qy + c.mx + c.my;
+  const C o11 = c.qx + c.qz - c.mx + c.mz;
+  const C o13 = c.qx - c.qz - c.mx - c.mz;
+  const C o15 = c.qy + c.qz + c.my - c.mz;
+  const C o17 = c.qy - c.qz + c.my + c.mz;
+  g[0] = g[0] - (C(-30.0) * c.e + C(12.0) * c.eps);
+  g[1] = g[1] - (ev_x + od_x);
+  g[2] = g[2] - (ev_x - od_x);
+  g[3] = g[3] - (ev_y + od_y);
+  g[4] = g[4] - (ev_y - od_y);
+  g[5] = g[5] - (ev_z + od_z);
+  g[6] = g[6] - (ev_z - od_z);
+  g[7] = g[7] - (ev_xy + c.pxy + o7);
+  g[8] = g[8] - (ev_xy + c.pxy - o7);
+  g[9] = g[9] - (ev_xy - c.pxy + o9);
+  g[10] = g[10] - (ev_xy - c.pxy - o9);
+  g[11] = g[11] - (ev_xz + c.pxz + o11);
+  g[12] = g[12] - (ev_xz + c.pxz - o11);
+  g[13] = g[13] - (ev_xz - c.pxz + o13);
+  g[14] = g[14] - (ev_xz - c.pxz - o13);
+  g[15] = g[15] - (ev_yz + c.pyz + o15);
+  g[16] = g[16] - (ev_yz + c.pyz - o15);
+  g[17] = g[17] - (ev_yz - c.pyz + o17);
+  g[18] = g[18] - (ev_yz - c.pyz - o17);
+}
+
+// m_eq on the non-conserved rows, minus the reference's moments, from the
+// recovered fields (closed forms of M g_eq with g_eq of Eqs. 8-9).
+template <typename C>
+__device__ __forceinline__ NonConserved<C> equilibrium_nc(const Macro& mac, const Ref& ref) {
+  const double sd = mac.sigma, Pd = mac.P, u2d = mac.u2;
+  const C sg = (C)sd;
+  const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)u2d;
+  const C sux = sg * ux, suy = sg * uy, suz = sg * uz;
+  NonConserved<C> q;
+  q.e = (C)(19.0 * sd * u2d + 87.0 * Pd - 30.0 * sd + 33.0 * ref.P);
+  q.eps = (C)(12.0 * sd - 39.0 * Pd - 5.5 * sd * u2d - 9.0 * ref.P);
+  q.qx = C(-2.0 / 3.0) * sux;
+  q.qy = C(-2.0 / 3.0) * suy;
+  q.qz = C(-2.0 / 3.0) * suz;
+  q.p3xx = sg * (C(3.0) * ux * ux - uu);
+  q.pi3xx = C(-0.5) * q.p3xx;
+  q.pww = sg * (uy * uy - uz * uz);
+  q.piww = C(-0.5) * q.pww;
+  q.pxy = sux * uy;
+  q.pxz = sux * uz;
+  q.pyz = suy * uz;
+  q.mx = q.my = q.mz = C(0.0);
+  return q;
+}
+
+// c_k = s_k v_k / |row_k|^2.
+template <typename C>
+__device__ __forceinline__ NonConserved<C> scale_rates(const NonConserved<C>& v, const Rates& rt) {
+  const C se = (C)rt.s_e, seps = (C)rt.s_eps, sq = (C)rt.s_q, sv = (C)rt.s_v;
+  NonConserved<C> c;
+  c.e = se * v.e * C(1.0 / kNormE);
+  c.eps = seps * v.eps * C(1.0 / kNormEps);
+  c.qx = sq * v.qx * C(1.0 / kNormQ);
+  c.qy = sq * v.qy * C(1.0 / kNormQ);
+  c.qz = sq * v.qz * C(1.0 / kNormQ);
+  c.p3xx = sv * v.p3xx * C(1.0 / kNorm3P);
+  c.pi3xx = sq * v.pi3xx * C(1.0 / kNorm3Pi);
+  c.pww = sv * v.pww * C(1.0 / kNormW);
+  c.piww = sq * v.piww * C(1.0 / kNormWPi);
+  c.pxy = sv * v.pxy * C(1.0 / kNormPxy);
+  c.pyz = sv * v.pyz * C(1.0 / kNormPxy);
+  c.pxz = sv * v.pxz * C(1.0 / kNormPxy);
+  c.mx = sq * v.mx * C(1.0 / kNormM);
+  c.my = sq * v.my * C(1.0 / kNormM);
+  c.mz = sq * v.mz * C(1.0 / kNormM);
+  return c;
+}
+
+template <typename C>
+__device__ __forceinline__ NonConserved<C> nc_sub(const NonConserved<C>& a,
+                                                  const NonConserved<C>& b) {
+  NonConserved<C> d;
+  d.e = a.e - b.e;
+  d.eps = a.eps - b.eps;
+  d.qx = a.qx - b.qx;
+  d.qy = a.qy - b.qy;
+  d.qz = a.qz - b.qz;
+  d.p3xx = a.p3xx - b.p3xx;
+  d.pi3xx = a.pi3xx - b.pi3xx;
+  d.pww = a.pww - b.pww;
+  d.piww = a.piww - b.piww;
+  d.pxy = a.pxy - b.pxy;
+  d.pyz = a.pyz - b.pyz;
+  d.pxz = a.pxz - b.pxz;
+  d.mx = a.mx - b.mx;
+  d.my = a.my - b.my;
+  d.mz = a.mz - b.mz;
+  return d;
+}
+
+// f: BGK, Eq. (5), in place. fs is the FP64 sum of the incoming stored f.
+template <typename C>
+__device__ __forceinline__ void collide_f(C (&f)[19], double N, double fs, const Macro& mac,
+                                          const Rates& rt, const Ref& ref) {
+  const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)mac.u2;
+  const C Nc = (C)N;
+  const C b = (C)(N - ref.n) - C(1.5) * Nc * uu;  // deviation part of the w-bracket
+  const C a3 = C(3.0) * Nc, a45 = C(4.5) * Nc;
+  const C wf = (C)rt.w_f;
+  const C w0 = C(1.0 / 3.0), w1 = C(1.0 / 18.0), w2 = C(1.0 / 36.0);
+  C eu[19];
+  eu[0] = C(0.0);
+  eu[1] = ux;
+  eu[2] = -ux;
+  eu[3] = uy;
+  eu[4] = -uy;
+  eu[5] = uz;
+  eu[6] = -uz;
+  eu[7] = ux + uy;
+  eu[8] = -(ux + uy);
+  eu[9] = ux - uy;
+  eu[10] = -(ux - uy);
+  eu[11] = ux + uz;
+  eu[12] = -(ux + uz);
+  eu[13] = ux - uz;
+  eu[14] = -(ux - uz);
+  eu[15] = uy + uz;
+  eu[16] = -(uy + uz);
+  eu[17] = uy - uz;
+  eu[18] = -(uy - uz);
 #pragma unroll
-    for (int a = 0; a < 19; ++a) {
-      const C w = a == 0 ? w0 : (a < 7 ? w1 : w2);
-      const C feq = w * (b + a3 * eu[a] + a45 * eu[a] * eu[a]);
-      f[a] = f[a] + wf * (feq - f[a]);
-    }
+  for (int a = 0; a < 19; ++a) {
+    const C w = a == 0 ? w0 : (a < 7 ? w1 : w2);
+    const C feq = w * (b + a3 * eu[a] + a45 * eu[a] * eu[a]);
+    f[a] = f[a] + wf * (feq - f[a]);
   }
-
-  // ---------------- g: MRT (Eqs. 30, 31, 35) ----------------
-  {
-    const C g0 = g[0];
-    const C S1 = g[1] + g[2], S3 = g[3] + g[4], S5 = g[5] + g[6];
-    const C S7 = g[7] + g[8], S9 = g[9] + g[10], S11 = g[11] + g[12];
-    const C S13 = g[13] + g[14], S15 = g[15] + g[16], S17 = g[17] + g[18];
-    const C D1 = g[1] - g[2], D3 = g[3] - g[4], D5 = g[5] - g[6];
-    const C D7 = g[7] - g[8], D9 = g[9] - g[10], D11 = g[11] - g[12];
-    const C D13 = g[13] - g[14], D15 = g[15] - g[16], D17 = g[17] - g[18];
-    const C Sf = S1 + S3 + S5;
-    const C Exy = S7 + S9, Exz = S11 + S13, Eyz = S15 + S17;
-    const C Se = Exy + Exz + Eyz;
-
-    // non-conserved moments of the stored deviations
-    const C m_e = C(-30.0) * g0 - C(11.0) * Sf + C(8.0) * Se;
-    const C m_eps = C(12.0) * g0 - C(4.0) * Sf + Se;
-    const C xyz_p = Exy + Exz - C(2.0) * Eyz;
-    const C m_3pxx = C(2.0) * S1 - S3 - S5 + xyz_p;
-    const C m_3pixx = C(-4.0) * S1 + C(2.0) * S3 + C(2.0) * S5 + xyz_p;
-    const C m_pww = S3 - S5 + Exy - Exz;
-    const C m_piww = C(-2.0) * S3 + C(2.0) * S5 + Exy - Exz;
-    const C m_pxy = S7 - S9, m_pxz = S11 - S13, m_pyz = S15 - S17;
-    const C m_qx = C(-4.0) * D1 + D7 + D9 + D11 + D13;
-    const C m_qy = C(-4.0) * D3 + D7 - D9 + D15 + D17;
-    const C m_qz = C(-4.0) * D5 + D11 - D13 + D15 - D17;
-    const C m_mx = D7 + D9 - D11 - D13;
-    const C m_my = -D7 + D9 + D15 + D17;
-    const C m_mz = D11 - D13 - D15 + D17;
-
-    // equilibrium moments minus the reference's (closed forms of M g_eq)
-    const double sd = mac.sigma, Pd = mac.P, u2d = mac.u2;
-    const C meq_e = (C)(19.0 * sd * u2d + 87.0 * Pd - 30.0 * sd + 33.0 * ref.P);
-    const C meq_eps = (C)(12.0 * sd - 39.0 * Pd - 5.5 * sd * u2d - 9.0 * ref.P);
-    const C sg = (C)sd;
-    const C ux = (C)mac.ux, uy = (C)mac.uy, uz = (C)mac.uz, uu = (C)u2d;
-    const C sux = sg * ux, suy = sg * uy, suz = sg * uz;
-    const C meq_3pxx = sg * (C(3.0) * ux * ux - uu);
-    const C meq_pww = sg * (uy * uy - uz * uz);
-    const C meq_q = C(-2.0 / 3.0);
-
-    // c_k = s_k (m_k - m_eq,k) / |row_k|^2
-    const C se = (C)rt.s_e, seps = (C)rt.s_eps, sq = (C)rt.s_q, sv = (C)rt.s_v;
-    const C ce = se * (m_e - meq_e) * C(1.0 / 2394.0);
-    const C ceps = seps * (m_eps - meq_eps) * C(1.0 / 252.0);
-    const C cqx = sq * (m_qx - meq_q * sux) * C(1.0 / 40.0);
-    const C cqy = sq * (m_qy - meq_q * suy) * C(1.0 / 40.0);
-    const C cqz = sq * (m_qz - meq_q * suz) * C(1.0 / 40.0);
-    const C cp = sv * (m_3pxx - meq_3pxx) * C(1.0 / 36.0);
-    const C cpi = sq * (m_3pixx + C(0.5) * meq_3pxx) * C(1.0 / 72.0);
-    const C cw = sv * (m_pww - meq_pww) * C(1.0 / 12.0);
-    const C cwpi = sq * (m_piww + C(0.5) * meq_pww) * C(1.0 / 24.0);
-    const C cxy = sv * (m_pxy - sux * uy) * C(0.25);
-    const C cxz = sv * (m_pxz - sux * uz) * C(0.25);
-    const C cyz = sv * (m_pyz - suy * uz) * C(0.25);
-    const C cmx = sq * m_mx * C(0.125);
-    const C cmy = sq * m_my * C(0.125);
-    const C cmz = sq * m_mz * C(0.125);
-
-    // g* = g - M^T c
-    const C face = C(-11.0) * ce - C(4.0) * ceps;
-    const C ev_x = face + C(2.0) * cp - C(4.0) * cpi;
-    const C ev_y = face - cp + C(2.0) * cpi + cw - C(2.0) * cwpi;
-    const C ev_z = face - cp + C(2.0) * cpi - cw + C(2.0) * cwpi;
-    const C edge = C(8.0) * ce + ceps;
-    const C ev_xy = edge + cp + cpi + cw + cwpi;
-    const C ev_xz = edge + cp + cpi - cw - cwpi;
-    const C ev_yz = edge - C(2.0) * (cp + cpi);
-    const C od_x = C(-4.0) * cqx, od_y = C(-4.0) * cqy, od_z = C(-4.0) * cqz;
-    const C o7 = cqx + cqy + cmx - cmy;
-    const C o9 = cqx - cqy + cmx + cmy;
-    const C o11 = cqx + cqz - cmx + cmz;
-    const C o13 = cqx - cqz - cmx - cmz;
-    const C o15 = cqy + cqz + cmy - cmz;
-    const C o17 = cqy - cqz + cmy + cmz;
-
-    g[0] = g0 - (C(-30.0) * ce + C(12.0) * ceps);
-    g[1] = g[1] - (ev_x + od_x);
-    g[2] = g[2] - (ev_x - od_x);
-    g[3] = g[3] - (ev_y + od_y);
-    g[4] = g[4] - (ev_y - od_y);
-    g[5] = g[5] - (ev_z + od_z);
-    g[6] = g[6] - (ev_z - od_z);
-    g[7] = g[7] - (ev_xy + cxy + o7);
-    g[8] = g[8] - (ev_xy + cxy - o7);
-    g[9] = g[9] - (ev_xy - cxy + o9);
-    g[10] = g[10] - (ev_xy - cxy - o9);
-    g[11] = g[11] - (ev_xz + cxz + o11);
-    g[12] = g[12] - (ev_xz + cxz - o11);
-    g[13] = g[13] - (ev_xz - cxz + o13);
-    g[14] = g[14] - (ev_xz - cxz - o13);
-    g[15] = g[15] - (ev_yz + cyz + o15);
-    g[16] = g[16] - (ev_yz + cyz - o15);
-    g[17] = g[17] - (ev_yz - cyz + o17);
-    g[18] = g[18] - (ev_yz - cyz - o17);
-  }
-
-  // FP32 storage: the conserved sums of the rounded outputs differ from the
-  // incoming ones by a rounding residual that is not zero on average (it
-  // builds up linearly over steps). It is folded back, computed in FP64:
-  // momentum into g_1, g_3, g_5 (one population per axis), then particle
-  // number into f_0 and energy into g_0 (rest populations carry no momentum).
-  // What remains is one rounding per population, with no bias.
+  // FP32 storage: the rounded outputs no longer sum to the incoming particle
+  // number, and the residual is not zero on average (it builds up linearly
+  // over steps). The rest population takes it back, computed in FP64.
   if constexpr (sizeof(C) == 4) {
     double fo = 0.0;
 #pragma unroll
     for (int a = 1; a < 19; ++a) fo += (double)f[a];
     f[0] = (C)(fs - fo);
+  }
+}
+
+// g: MRT, Eqs. (30), (35), in place. (E, M, gs) are the FP64 sums of the
+// incoming stored g.
+template <typename C>
+__device__ __forceinline__ void collide_g(C (&g)[19], double Mx, double My, double Mz,
+                                          double gs, const Macro& mac, const Rates& rt,
+                                          const Ref& ref) {
+  const NonConserved<C> m = moments_nc(g);
+  const NonConserved<C> q = equilibrium_nc<C>(mac, ref);
+  sub_MT(g, scale_rates(nc_sub(m, q), rt));
+  // FP32 storage: as for f, the rounding residual of the conserved sums is
+  // folded back in FP64: momentum into g_1, g_3, g_5 (one population per
+  // axis), then energy into g_0 (the rest population carries no momentum).
+  if constexpr (sizeof(C) == 4) {
     double gd[19];
 #pragma unroll
     for (int a = 1; a < 19; ++a) gd[a] = (double)g[a];
@@ -298,6 +359,36 @@ __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt,
     for (int a = 1; a < 19; ++a) go += gd[a];
     g[0] = (C)(gs - go);
   }
+}
+
+// One collision of both distributions in place on the stored deviations.
+// Returns admissibility; sums receives the FP64 Eq. (10) sums of the incoming
+// populations.
+template <typename C>
+__device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt, const Ref& ref,
+                                        Sums& sums) {
+  double N, E, Mx, My, Mz, fs, gs;
+  cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
+  sums.v[0] = N;
+  sums.v[1] = E;
+  sums.v[2] = Mx;
+  sums.v[3] = My;
+  sums.v[4] = Mz;
+  Macro mac;
+  if (!recover(E, Mx, My, Mz, mac)) return false;
+  collide_f(f, N, fs, mac, rt, ref);
+  collide_g(g, Mx, My, Mz, gs, mac, rt, ref);
+  return true;
+}
+
+// The g half alone (g never reads f): bit-identical to the g of collide().
+template <typename C>
+__device__ __forceinline__ bool collide_g_only(C (&g)[19], const Rates& rt, const Ref& ref) {
+  double E, Mx, My, Mz, gs;
+  g_sums(g, ref, E, Mx, My, Mz, gs);
+  Macro mac;
+  if (!recover(E, Mx, My, Mz, mac)) return false;
+  collide_g(g, Mx, My, Mz, gs, mac, rt, ref);
   return true;
 }
 
