@@ -34,7 +34,8 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM roofline, FP32 vs FP64 step, batched and adjoint, at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1211_3286_amd", "csrc", f)
-                  for f in ("cell.hpp", "kernels.hip")]
+                  for f in ("cell.hpp", "device_util.hpp", "internal.hpp", "kernels.hip",
+                            "api.cpp")]
 
 
 def log(*a):
@@ -193,6 +194,54 @@ def cpu_baseline(prob, seconds: float):
                       f"{prob.params.nz} lattice (after 1 untimed step), {dt:.1f} s"}
 
 
+def summarize_trace(csv_path: str, command: str) -> str:
+    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(csv_path)))
+    out = [f"Command: `{command}`", "",
+           "| kernel | calls | average (us) | min (us) | max (us) | total (ms) | % |",
+           "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        name = r["Name"].replace("rlb::(anonymous namespace)::", "").replace("void ", "")
+        name = name.split("(")[0]
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict:
+    """HBM bytes per dispatch of every step-kernel variant from two PMC runs
+    (FETCH_SIZE, WRITE_SIZE in KiB), each scaled by what the same counter
+    reads for the 1 GiB plain copy of --copy-calibration."""
+    import collections
+    import csv
+    vals = collections.defaultdict(list)
+    for path in (fetch_csv, write_csv):
+        for r in csv.DictReader(open(path)):
+            vals[(r["Kernel_Name"], r["Grid_Size"], r["Counter_Name"])].append(
+                float(r["Counter_Value"]) * 1024.0)
+    copy = {c: sum(v) / len(v) for (k, g, c), v in vals.items()
+            if "copyBuffer" in k and g == "131072"}
+    scale = {c: (1 << 30) / copy[c] for c in copy}
+    out = {"_calibration": {"copy_bytes": 1 << 30, "counter_bytes": copy, "scale": scale}}
+    for (k, g, c), v in vals.items():
+        if "k_step_lattice" not in k:
+            continue
+        name = k.replace("void rlb::(anonymous namespace)::", "").split("(")[0]
+        name = name.replace(", ", ",").replace(",true>", ">").replace(",false>", ">")
+        rec = out.setdefault(name, {"cells": cells, "source_hash": kernel_hash()})
+        rec[c.lower() + "_bytes"] = sum(v) / len(v) * scale[c]
+    for name, rec in out.items():
+        if name.startswith("_") or "fetch_size_bytes" not in rec or "write_size_bytes" not in rec:
+            continue
+        esz = 4 if "float" in name else 8
+        rec["bytes_per_launch"] = rec["fetch_size_bytes"] + rec["write_size_bytes"]
+        rec["algorithmic_bytes"] = 2 * 38 * esz * cells
+        rec["ratio"] = rec["bytes_per_launch"] / rec["algorithmic_bytes"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,7 +256,20 @@ def main():
                     help="fuse the FP64 conservation sums into every N-th step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
+                    help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two PMC runs and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.write_traffic:
+        rec = write_traffic(*args.write_traffic)
+        with open(TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1, sort_keys=True)
+        print(json.dumps(rec, indent=1, sort_keys=True))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "slab decomposition is a design, not part of this build", file=sys.stderr)
