@@ -30,8 +30,9 @@ struct Layout {
   int64_t ncells = 0, cs = 0;
   size_t esz = 0;
   size_t off_descs = 0, off_small = 0, off_partials = 0, off_buf0 = 0, off_buf1 = 0;
-  size_t off_stage = 0, off_tape = 0, total = 0;
+  size_t off_stage = 0, off_segs = 0, off_flags = 0, off_tape = 0, total = 0;
   int max_parts = 0;
+  int64_t max_segs = 0;  // persistent path: one segment per z-plane at most
   rlb::TapeLayout tape;
 };
 
@@ -89,6 +90,10 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
       parts = std::max(parts, rlb::lattice_partials(v, g));
   }
   parts = std::max<int64_t>(parts, (int64_t)n * rlb::kRefBlocks);
+  if (!lattice_path(n, L.ncells)) {
+    for (int i = 0; i < n; ++i) L.max_segs += m[i].nz;
+    parts = std::max<int64_t>(parts, L.max_segs);
+  }
   L.max_parts = std::max(parts, 1);
   size_t o = 0;
   L.off_descs = o;
@@ -104,6 +109,10 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   o = align_up(o + buf);
   L.off_stage = o;
   o = align_up(o + sizeof(double) * 8 * (size_t)L.ncells);
+  L.off_segs = o;
+  o = align_up(o + sizeof(rlb::Segment) * (size_t)L.max_segs);
+  L.off_flags = o;
+  o = align_up(o + sizeof(unsigned long long) * (size_t)L.max_segs);
   L.off_tape = o;
   if (opt->ckpt_every > 0) {
     L.tape = rlb::tape_layout(L.ncells, L.cs, L.esz, opt->ckpt_every, opt->tape_steps,
@@ -157,12 +166,20 @@ struct rlb_sim {
   int64_t steps = 0;
   int64_t diag_step = -1;
   int diag_parts = 0;
-  // persistent-kernel graph
+  // persistent kernels and their graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipGraphNode_t gnode = nullptr;
-  int graph_variant = -1;
+  const void* graph_func = nullptr;
   rlb::MemberLaunch margs{};
+  rlb::SegLaunch sargs{};
+  rlb::Segment* d_segs = nullptr;
+  unsigned long long* d_flags = nullptr;
+  int* d_error = nullptr;
+  unsigned long long epoch = 0;  // steps every segment flag holds
+  int seg_built = -1;             // segment variant the device table describes
+  int nseg = 0;
+  int num_cu = 0;
   // tape
   rlb::Tape tape{};
   bool tape_ok = false;
@@ -186,33 +203,112 @@ rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* s
                                           h->d_partials, h->d_bad, h->stream));
 }
 
-// Persistent member kernel through its graph (built on first use; later calls
-// only update the node's arguments).
-rlb_status launch_members_graph(rlb_sim* h, int nsteps, int pingpong, void* a, void* b,
-                                int diag_every, int64_t step0) {
-  rlb::MemberLaunch& m = h->margs;
-  m.descs = h->d_descs;
-  m.bufA = a;
-  m.bufB = b;
-  m.cs = h->L.cs;
-  m.nsteps = nsteps;
-  m.pingpong = pingpong;
-  m.diag_every = diag_every;
-  m.step0 = step0;
-  m.partials = h->d_partials;
-  m.bad = h->d_bad;
+constexpr int kSpinLimit = 1 << 24;  // about a second of polling per wait
+
+bool is_segment_variant(const rlb_sim* h, int v) {
+  return !h->lattice && v >= rlb::num_member_variants();
+}
+
+// Cut every member into segments of whole z-planes of about nt * cpt cells
+// (one pass of the block per step) and upload the table.
+rlb_status build_segments(rlb_sim* h, int sv) {
+  const rlb::MemberVariant mv = rlb::segment_variant(sv);
+  const int64_t target = (int64_t)mv.nt * mv.cpt;
+  std::vector<rlb::Segment> segs;
+  for (int m = 0; m < h->n_members; ++m) {
+    const MemberDesc& d = h->descs[m];
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    const int64_t want = std::max<int64_t>(1, (d.ncells + target - 1) / target);
+    const int nsm = (int)std::min<int64_t>(want, d.nz);
+    const int first = (int)segs.size();
+    for (int j = 0; j < nsm; ++j) {
+      rlb::Segment g{};
+      g.member = m;
+      g.z0 = (int)((int64_t)d.nz * j / nsm);
+      g.z1 = (int)((int64_t)d.nz * (j + 1) / nsm);
+      const bool wrap = d.bcz == RLB_PERIODIC && nsm > 1;
+      g.left = j > 0 ? first + j - 1 : (wrap ? first + nsm - 1 : -1);
+      g.right = j < nsm - 1 ? first + j + 1 : (wrap ? first : -1);
+      segs.push_back(g);
+      (void)plane;
+    }
+  }
+  if ((int64_t)segs.size() > h->L.max_segs) return RLB_E_ARG;
+  RLB_HIP(hipMemcpyAsync(h->d_segs, segs.data(), sizeof(rlb::Segment) * segs.size(),
+                         hipMemcpyHostToDevice, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  h->nseg = (int)segs.size();
+  h->seg_built = sv;
+  return RLB_OK;
+}
+
+// Every block of a segment launch must be resident at once (they wait on
+// each other); variants whose segments do not fit are refused.
+rlb_status segments_fit(rlb_sim* h, int sv, const void* func, int nt) {
+  if (h->seg_built != sv) {
+    rlb_status st = build_segments(h, sv);
+    if (st != RLB_OK) return st;
+  }
+  int per_cu = 0;
+  RLB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, func, nt, 0));
+  if ((int64_t)per_cu * h->num_cu < h->nseg) return RLB_E_UNSUPPORTED;
+  return RLB_OK;
+}
+
+// Persistent kernels run from a one-node HIP graph (built on first use, and
+// again when the kernel changes; later calls only update the arguments).
+rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
+                             int diag_every, int64_t step0) {
   const void* func;
-  dim3 block;
-  RLB_HIP(rlb::member_kernel(h->precision, h->variant, &func, &block));
-  void* args[] = {&h->margs};
+  dim3 block, grid;
+  void* args[1];
+  if (is_segment_variant(h, variant)) {
+    const int sv = variant - rlb::num_member_variants();
+    RLB_HIP(rlb::segment_kernel(h->precision, sv, &func, &block));
+    rlb_status st = segments_fit(h, sv, func, block.x);
+    if (st != RLB_OK) return st;
+    rlb::SegLaunch& g = h->sargs;
+    g.descs = h->d_descs;
+    g.segs = h->d_segs;
+    g.bufA = a;
+    g.bufB = b;
+    g.cs = h->L.cs;
+    g.nsteps = nsteps;
+    g.pingpong = pingpong;
+    g.diag_every = diag_every;
+    g.spin_limit = kSpinLimit;
+    g.step0 = step0;
+    g.epoch = h->epoch;
+    g.flags = h->d_flags;
+    g.error = h->d_error;
+    g.partials = h->d_partials;
+    g.bad = h->d_bad;
+    args[0] = &h->sargs;
+    grid = dim3(h->nseg, 1, 1);
+  } else {
+    rlb::MemberLaunch& m = h->margs;
+    m.descs = h->d_descs;
+    m.bufA = a;
+    m.bufB = b;
+    m.cs = h->L.cs;
+    m.nsteps = nsteps;
+    m.pingpong = pingpong;
+    m.diag_every = diag_every;
+    m.step0 = step0;
+    m.partials = h->d_partials;
+    m.bad = h->d_bad;
+    RLB_HIP(rlb::member_kernel(h->precision, variant, &func, &block));
+    args[0] = &h->margs;
+    grid = dim3(h->n_members, 1, 1);
+  }
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(func);
-  kp.gridDim = dim3(h->n_members, 1, 1);
+  kp.gridDim = grid;
   kp.blockDim = block;
   kp.sharedMemBytes = 0;
   kp.kernelParams = args;
   kp.extra = nullptr;
-  if (h->gexec && h->graph_variant != h->variant) {
+  if (h->gexec && h->graph_func != func) {
     (void)hipGraphExecDestroy(h->gexec);
     (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
@@ -222,11 +318,12 @@ rlb_status launch_members_graph(rlb_sim* h, int nsteps, int pingpong, void* a, v
     RLB_HIP(hipGraphCreate(&h->graph, 0));
     RLB_HIP(hipGraphAddKernelNode(&h->gnode, h->graph, nullptr, 0, &kp));
     RLB_HIP(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
-    h->graph_variant = h->variant;
+    h->graph_func = func;
   } else {
     RLB_HIP(hipGraphExecKernelNodeSetParams(h->gexec, h->gnode, &kp));
   }
   RLB_HIP(hipGraphLaunch(h->gexec, h->stream));
+  if (is_segment_variant(h, variant)) h->epoch += (unsigned long long)nsteps;
   return RLB_OK;
 }
 
@@ -249,11 +346,11 @@ rlb_status advance(rlb_sim* h, int32_t n) {
     }
     return RLB_OK;
   }
-  rlb_status st = launch_members_graph(h, n, 1, state_buf(h), spare_buf(h), D, h->steps);
+  rlb_status st = launch_persistent(h, h->variant, n, 1, state_buf(h), spare_buf(h), D, h->steps);
   if (st != RLB_OK) return st;
   if (D > 0) {
     h->diag_step = h->steps + n;
-    h->diag_parts = h->n_members;
+    h->diag_parts = is_segment_variant(h, h->variant) ? h->nseg : h->n_members;
   }
   h->steps += n;
   if (n & 1) h->cur = 1 - h->cur;
@@ -289,6 +386,25 @@ bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int6
       return false;
   }
   return true;
+}
+
+}  // namespace
+
+namespace {
+
+const char* kernel_name_of(const rlb_sim* h, int v) {
+  if (h->lattice) return rlb::lattice_kernel_name(h->precision, v);
+  if (v < rlb::num_member_variants()) return rlb::member_kernel_name(h->precision, v);
+  return rlb::segment_kernel_name(h->precision, v - rlb::num_member_variants());
+}
+
+// A persistent segment launch whose neighbour wait timed out leaves a sticky
+// error word; it is reported at the next synchronising call.
+rlb_status persistent_error(rlb_sim* h) {
+  int e = 0;
+  RLB_HIP(hipMemcpyAsync(&e, h->d_error, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  return e ? RLB_E_DEVICE : RLB_OK;
 }
 
 }  // namespace
@@ -357,6 +473,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->buf[0] = h->ws + L.off_buf0;
   h->buf[1] = h->ws + L.off_buf1;
   h->d_stage = (double*)(h->ws + L.off_stage);
+  h->d_segs = (rlb::Segment*)(h->ws + L.off_segs);
+  h->d_flags = (unsigned long long*)(h->ws + L.off_flags);
+  h->d_error = (int*)(h->d_small + 24);
   h->lattice = lattice_path(n_members, L.ncells);
   h->variant = h->lattice ? 3 : 2;
 
@@ -389,6 +508,13 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   }
   const double *dn, *de, *du;
   if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess) return fail(RLB_E_DEVICE);
+  if (L.max_segs > 0 &&
+      hipMemsetAsync(h->d_flags, 0, sizeof(unsigned long long) * L.max_segs, h->stream) !=
+          hipSuccess)
+    return fail(RLB_E_DEVICE);
+  if (hipDeviceGetAttribute(&h->num_cu, hipDeviceAttributeMultiprocessorCount, h->device) !=
+      hipSuccess)
+    return fail(RLB_E_DEVICE);
   if (copy_fields_in(h, n0, eps0, u0, fields_on_device, &dn, &de, &du) != RLB_OK)
     return fail(RLB_E_DEVICE);
   if (fields_on_device) {
@@ -503,6 +629,7 @@ rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* 
   RLB_HIP(hipStreamSynchronize(h->stream));
   if (sums) std::memcpy(sums, hs, sizeof(hs));
   if (n_unphysical) *n_unphysical = (int64_t)bad;
+  if (persistent_error(h) != RLB_OK) return RLB_E_DEVICE;
   return bad ? RLB_E_UNPHYSICAL : RLB_OK;
 }
 
@@ -520,7 +647,7 @@ rlb_status rlb_diagnostics(rlb_handle h, double sums[5], int64_t* step, int64_t*
   if (sums) std::memcpy(sums, hs, sizeof(hs));
   if (step) *step = h->diag_step;
   if (n_unphysical) *n_unphysical = (int64_t)bad;
-  return RLB_OK;
+  return persistent_error(h);
 }
 
 rlb_status rlb_populations(rlb_handle h, double* f, double* g, int32_t out_on_device) {
@@ -554,7 +681,7 @@ rlb_status rlb_populations(rlb_handle h, double* f, double* g, int32_t out_on_de
     }
   }
   RLB_HIP(hipStreamSynchronize(h->stream));
-  return RLB_OK;
+  return persistent_error(h);
 }
 
 rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
@@ -580,7 +707,8 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
 
 rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
   if (!h || !count) return RLB_E_ARG;
-  *count = h->lattice ? rlb::num_lattice_variants() : rlb::num_member_variants();
+  *count = h->lattice ? rlb::num_lattice_variants()
+                      : rlb::num_member_variants() + rlb::num_segment_variants();
   return RLB_OK;
 }
 
@@ -588,9 +716,7 @@ rlb_status rlb_variant_name(rlb_handle h, int32_t v, char* buf, size_t buflen) {
   int32_t n;
   if (rlb_num_variants(h, &n) != RLB_OK || !buf || buflen == 0) return RLB_E_ARG;
   if (v < 0 || v >= n) return RLB_E_ARG;
-  const char* s = h->lattice ? rlb::lattice_kernel_name(h->precision, v)
-                             : rlb::member_kernel_name(h->precision, v);
-  std::snprintf(buf, buflen, "%s", s);
+  std::snprintf(buf, buflen, "%s", kernel_name_of(h, v));
   return RLB_OK;
 }
 
@@ -627,26 +753,33 @@ rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
   rlb_status st = RLB_OK;
   for (int v = 0; v < n && st == RLB_OK; ++v) {
     float ms = 0.0f;
-    h->variant = v;
-    for (int rep = 0; rep < 2 && st == RLB_OK; ++rep) {  // rep 0 warms up
+    bool usable = true;
+    for (int rep = 0; rep < 2 && st == RLB_OK && usable; ++rep) {  // rep 0 warms up
       if (hipEventRecord(e0, h->stream) != hipSuccess) st = RLB_E_DEVICE;
       if (h->lattice) {
         for (int i = 0; i < trial_steps && st == RLB_OK; ++i)
           st = launch_lattice_step(h, v, false, state_buf(h), spare_buf(h));
       } else if (st == RLB_OK) {
-        st = launch_members_graph(h, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0);
+        st = launch_persistent(h, v, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0);
+        if (st == RLB_E_UNSUPPORTED) {  // segments do not all fit at once
+          usable = false;
+          st = RLB_OK;
+        }
       }
-      if (st == RLB_OK && hipEventRecord(e1, h->stream) != hipSuccess) st = RLB_E_DEVICE;
-      if (st == RLB_OK && hipEventSynchronize(e1) != hipSuccess) st = RLB_E_DEVICE;
-      if (st == RLB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = RLB_E_DEVICE;
+      if (st == RLB_OK && usable && hipEventRecord(e1, h->stream) != hipSuccess)
+        st = RLB_E_DEVICE;
+      if (st == RLB_OK && usable && hipEventSynchronize(e1) != hipSuccess) st = RLB_E_DEVICE;
+      if (st == RLB_OK && usable && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        st = RLB_E_DEVICE;
     }
-    const double per = (double)ms / trial_steps;
+    const double per = usable ? (double)ms / trial_steps : HUGE_VAL;
     if (ms_per_step) ms_per_step[v] = per;
-    if (st == RLB_OK && per < best_ms) {
+    if (st == RLB_OK && usable && per < best_ms) {
       best_ms = per;
       best = v;
     }
   }
+  if (st == RLB_OK) st = persistent_error(h);
   (void)hipMemcpyAsync(h->d_bad, h->d_bad_save, sizeof(unsigned long long),
                        hipMemcpyDeviceToDevice, h->stream);
   (void)hipStreamSynchronize(h->stream);
@@ -661,9 +794,7 @@ rlb_status rlb_info(rlb_handle h, int64_t* steps, char* kernel_name, size_t bufl
   if (!h) return RLB_E_ARG;
   if (steps) *steps = h->steps;
   if (kernel_name && buflen)
-    std::snprintf(kernel_name, buflen, "%s",
-                  h->lattice ? rlb::lattice_kernel_name(h->precision, h->variant)
-                             : rlb::member_kernel_name(h->precision, h->variant));
+    std::snprintf(kernel_name, buflen, "%s", kernel_name_of(h, h->variant));
   return RLB_OK;
 }
 

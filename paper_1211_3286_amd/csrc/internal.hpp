@@ -73,6 +73,37 @@ struct MemberLaunch {
   unsigned long long* bad;
 };
 hipError_t member_kernel(int precision, int variant, const void** func, dim3* block);
+
+// Segmented persistent step: every member is cut into segments of whole
+// z-planes, one block per segment; a segment waits (per step) for the two
+// segments whose planes it pulls from. flags[s] counts the steps segment s has
+// completed; all flags equal `epoch` when a launch starts.
+struct Segment {
+  int32_t member;
+  int32_t z0, z1;       // planes [z0, z1) of the member
+  int32_t left, right;  // segments owning planes z0-1 and z1 (-1: none / self)
+};
+struct SegLaunch {
+  const MemberDesc* descs;
+  const Segment* segs;
+  void* bufA;
+  void* bufB;
+  int64_t cs;
+  int32_t nsteps;
+  int32_t pingpong;
+  int32_t diag_every;
+  int32_t spin_limit;  // polls before a wait gives up and flags an error
+  int64_t step0;
+  unsigned long long epoch;
+  unsigned long long* flags;
+  int* error;
+  double* partials;
+  unsigned long long* bad;
+};
+int num_segment_variants();
+MemberVariant segment_variant(int i);  // (threads per block, cells per thread)
+hipError_t segment_kernel(int precision, int variant, const void** func, dim3* block);
+const char* segment_kernel_name(int precision, int variant);
 hipError_t launch_step_members(int precision, int variant, int n_members, const MemberLaunch& a,
                                hipStream_t s);
 hipError_t launch_export(int precision, const void* state, int64_t cs, const MemberDesc* descs,

@@ -85,6 +85,7 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
   const int tid = threadIdx.x;
   const uint32_t esz = sizeof(T);
   const uint32_t base = (uint32_t)d.offset;
+  const bool tube = d.nx == 1 && d.ny == 1;
   int nbad = 0;
   for (int t = 0; t < a.nsteps; ++t) {
     const bool odd = a.pingpong && (t & 1);
@@ -98,10 +99,13 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
       for (int k = 0; k < CPT; ++k) {
         const int c = c0 + k * NT + tid;
         if (c < d.ncells) {
-          const int x = c % d.nx;
-          const int yz = c / d.nx;
-          const int y = yz % d.ny;
-          const int z = yz / d.ny;
+          int x = 0, y = 0, z = c;  // quasi-1D member (1 x 1 x L): no division
+          if (!tube) {
+            x = c % d.nx;
+            const int yz = c / d.nx;
+            y = yz % d.ny;
+            z = yz / d.ny;
+          }
           uint32_t off[19], self;
           pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, base, esz, off, self);
           T f[19], g[19];
@@ -130,6 +134,102 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
         for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
     }
     __syncthreads();
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
+// -------------------------------------------------------------------------
+// Segmented persistent step over a batch: one block per segment (a range of
+// whole z-planes of one member), all nsteps inside the launch. Before step t
+// a segment waits until its two neighbour segments have completed t steps
+// (their planes z0-1 and z1 are pulled, and they read this segment's planes
+// of the buffer it is about to overwrite). After its step every thread
+// makes its stores visible device-wide before thread 0 publishes the flag
+// with release semantics. A wait that exceeds spin_limit polls sets *error
+// and ends the launch for that block (every block reaches the exit).
+// -------------------------------------------------------------------------
+__device__ __forceinline__ bool wait_flag(const unsigned long long* f, unsigned long long target,
+                                          int spin_limit) {
+  for (int i = 0; i < spin_limit; ++i) {
+    if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
+}
+
+template <typename T, int NT, int CPT>
+__global__ __launch_bounds__(NT) void k_step_segments(SegLaunch a) {
+  const Segment sg = a.segs[blockIdx.x];
+  const MemberDesc d = a.descs[sg.member];
+  const int tid = threadIdx.x;
+  const uint32_t esz = sizeof(T);
+  const uint32_t base = (uint32_t)d.offset;
+  const int plane = d.nx * d.ny;
+  const bool tube = plane == 1;
+  const int c_begin = sg.z0 * plane, c_end = sg.z1 * plane;
+  __shared__ int s_abort;
+  int nbad = 0;
+  for (int t = 0; t < a.nsteps; ++t) {
+    const unsigned long long target = a.epoch + (unsigned long long)t;
+    if (tid == 0) {
+      bool ok = true;
+      if (sg.left >= 0) ok = wait_flag(a.flags + sg.left, target, a.spin_limit);
+      if (ok && sg.right >= 0) ok = wait_flag(a.flags + sg.right, target, a.spin_limit);
+      s_abort = ok ? 0 : 1;
+      if (!ok) atomicOr(a.error, 1);
+    }
+    __syncthreads();
+    if (s_abort) break;
+    const bool odd = a.pingpong && (t & 1);
+    const T* __restrict__ src = (const T*)(odd ? a.bufB : a.bufA);
+    T* __restrict__ dst = (T*)(odd ? a.bufA : a.bufB);
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag = a.diag_every > 0 && ((sidx % a.diag_every) == 0 || t == a.nsteps - 1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = c_begin; c0 < c_end; c0 += NT * CPT) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int c = c0 + k * NT + tid;
+        if (c < c_end) {
+          int x = 0, y = 0, z = c;  // quasi-1D member (1 x 1 x L): no division
+          if (!tube) {
+            x = c % d.nx;
+            const int yz = c / d.nx;
+            y = yz % d.ny;
+            z = yz / d.ny;
+          }
+          uint32_t off[19], self;
+          pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, base, esz, off, self);
+          T f[19], g[19];
+#pragma unroll
+          for (int q = 0; q < 19; ++q) {
+            f[q] = ld(src + (int64_t)q * a.cs, off[q]);
+            g[q] = ld(src + (int64_t)(19 + q) * a.cs, off[q]);
+          }
+          Sums s;
+          const bool ok = collide<T>(f, g, d.rt, d.ref, s);
+          nbad += ok ? 0 : 1;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+          for (int q = 0; q < 19; ++q) {
+            st(dst + (int64_t)q * a.cs, self, f[q]);
+            st(dst + (int64_t)(19 + q) * a.cs, self, g[q]);
+          }
+        }
+      }
+    }
+    if (diag) {
+      block_sum5<NT>(acc, tid);
+      if (tid == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_store(a.flags + blockIdx.x, target + 1ull, __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
   }
   if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
 }
@@ -291,6 +391,21 @@ constexpr int kNumLat = sizeof(kLat) / sizeof(kLat[0]);
 constexpr MemberVariant kMem[] = {{256, 1}, {512, 1}, {1024, 1}, {256, 2}, {512, 2}, {1024, 2}};
 constexpr int kNumMem = sizeof(kMem) / sizeof(kMem[0]);
 
+constexpr MemberVariant kSeg[] = {{256, 1}, {256, 2}, {512, 1}, {128, 4}, {256, 4}};
+constexpr int kNumSeg = sizeof(kSeg) / sizeof(kSeg[0]);
+
+template <typename T>
+const void* seg_func(int v) {
+  switch (v) {
+    case 0: return (const void*)&k_step_segments<T, 256, 1>;
+    case 1: return (const void*)&k_step_segments<T, 256, 2>;
+    case 2: return (const void*)&k_step_segments<T, 512, 1>;
+    case 3: return (const void*)&k_step_segments<T, 128, 4>;
+    case 4: return (const void*)&k_step_segments<T, 256, 4>;
+  }
+  return nullptr;
+}
+
 int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -344,6 +459,26 @@ const void* mem_func(int v) {
 }  // namespace
 
 int num_lattice_variants() { return kNumLat; }
+int num_segment_variants() { return kNumSeg; }
+MemberVariant segment_variant(int i) { return kSeg[i]; }
+
+hipError_t segment_kernel(int precision, int v, const void** func, dim3* block) {
+  if (v < 0 || v >= kNumSeg) return hipErrorInvalidValue;
+  *func = precision ? seg_func<float>(v) : seg_func<double>(v);
+  *block = dim3(kSeg[v].nt, 1, 1);
+  return hipSuccess;
+}
+
+const char* segment_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_step_segments<float,256,1>", "k_step_segments<float,256,2>",
+                              "k_step_segments<float,512,1>", "k_step_segments<float,128,4>",
+                              "k_step_segments<float,256,4>"};
+  static const char* n64[] = {"k_step_segments<double,256,1>", "k_step_segments<double,256,2>",
+                              "k_step_segments<double,512,1>", "k_step_segments<double,128,4>",
+                              "k_step_segments<double,256,4>"};
+  if (v < 0 || v >= kNumSeg) return "?";
+  return precision ? n32[v] : n64[v];
+}
 LatticeVariant lattice_variant(int i) { return kLat[i]; }
 int num_member_variants() { return kNumMem; }
 MemberVariant member_variant(int i) { return kMem[i]; }

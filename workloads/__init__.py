@@ -255,18 +255,21 @@ def blast(L: int = 512, radius: float | None = None, shell: float | None = None,
     shape = (L, L, L)
     c = (L - 1) / 2.0
     ax = np.arange(L, dtype=np.float64) - c
-    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
-    r = np.sqrt(X * X + Y * Y + Z * Z)
+    r = np.sqrt(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2)
     P = P_out + (P_in - P_out) * 0.5 * (1.0 - np.tanh((r - R) / width))
     n = P ** 0.75
-    noise = _noise(rng, shape)
-    mag = np.exp(-((r - R) / w) ** 2) * (1.0 + 0.1 * noise)
+    mag = np.exp(-((r - R) / w) ** 2) * (1.0 + 0.1 * _noise(rng, shape))
     rs = np.where(r > 0, r, 1.0)
-    u = np.stack([mag * X / rs, mag * Y / rs, mag * Z / rs])
+    del r
+    u = np.empty((3,) + shape)
+    u[0] = mag * ax[None, None, :] / rs
+    u[1] = mag * ax[None, :, None] / rs
+    u[2] = mag * ax[:, None, None] / rs
+    del mag, rs
     u *= umax / np.sqrt((u * u).sum(axis=0)).max()
     tf = tau_v if tau_f is None else tau_f
     prm = Params(L, L, L, (ZERO_GRADIENT,) * 3, tf, tau_v, tau_e, tau_eps)
-    return Problem(prm, n, 3.0 * P, u, name=f"blast_{L}^3")
+    return Problem(prm, n, 3.0 * P, u, name=f"blast_{L}x{L}x{L}")
 
 
 def uniform(nx: int, ny: int, nz: int, n: float = 1.0, eps: float = 1.0,
