@@ -110,7 +110,7 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   L.off_stage = o;
   o = align_up(o + sizeof(double) * 8 * (size_t)L.ncells);
   L.off_segs = o;
-  o = align_up(o + sizeof(rlb::Segment) * (size_t)L.max_segs);
+  o = align_up(o + std::max(sizeof(rlb::Segment), sizeof(rlb::TubeSeg)) * (size_t)L.max_segs);
   L.off_flags = o;
   o = align_up(o + sizeof(unsigned long long) * (size_t)L.max_segs);
   L.off_tape = o;
@@ -177,7 +177,10 @@ struct rlb_sim {
   unsigned long long* d_flags = nullptr;
   int* d_error = nullptr;
   unsigned long long epoch = 0;  // steps every segment flag holds
-  int seg_built = -1;             // segment variant the device table describes
+  int seg_built = -1;             // segment (or tube) variant the device table describes
+  hipGraph_t tgraph = nullptr;    // chain of tube rounds of the last rlb_step
+  hipGraphExec_t tgexec = nullptr;
+  bool all_tubes = false;
   int nseg = 0;
   int num_cu = 0;
   // tape
@@ -206,7 +209,116 @@ rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* s
 constexpr int kSpinLimit = 1 << 24;  // about a second of polling per wait
 
 bool is_segment_variant(const rlb_sim* h, int v) {
-  return !h->lattice && v >= rlb::num_member_variants();
+  return !h->lattice && v >= rlb::num_member_variants() &&
+         v < rlb::num_member_variants() + rlb::num_segment_variants();
+}
+
+bool is_tube_variant(const rlb_sim* h, int v) {
+  return !h->lattice && v >= rlb::num_member_variants() + rlb::num_segment_variants();
+}
+
+int tube_index(int v) { return v - rlb::num_member_variants() - rlb::num_segment_variants(); }
+
+// Tube segments for a tube variant: owned ranges of at most NT - 2H cells,
+// windows extended by H halo cells (cut at zero-gradient ends); a tube that
+// fits the block whole is one segment with exact ends.
+rlb_status build_tube_segments(rlb_sim* h, int tv) {
+  const rlb::TubeVariant v = rlb::tube_variant(tv);
+  const int S = v.nt - 2 * v.halo;
+  std::vector<rlb::TubeSeg> segs;
+  for (int m = 0; m < h->n_members; ++m) {
+    const MemberDesc& d = h->descs[m];
+    const int L = d.nz;
+    const bool periodic = d.bcz == RLB_PERIODIC;
+    if (L <= v.nt) {
+      const int kind = periodic ? rlb::kEdgeWrap : rlb::kEdgeClamp;
+      segs.push_back(rlb::TubeSeg{m, 0, L, 0, L, kind, kind});
+      continue;
+    }
+    const int n = (L + S - 1) / S;
+    for (int j = 0; j < n; ++j) {
+      rlb::TubeSeg g{};
+      g.member = m;
+      g.own0 = (int)((int64_t)L * j / n);
+      g.own1 = (int)((int64_t)L * (j + 1) / n);
+      if (periodic) {
+        g.win0 = g.own0 - v.halo;
+        g.wlen = g.own1 - g.own0 + 2 * v.halo;
+        g.left = g.right = rlb::kEdgeHalo;
+      } else {
+        g.win0 = std::max(0, g.own0 - v.halo);
+        const int win1 = std::min(L, g.own1 + v.halo);
+        g.wlen = win1 - g.win0;
+        g.left = g.win0 == 0 ? rlb::kEdgeClamp : rlb::kEdgeHalo;
+        g.right = win1 == L ? rlb::kEdgeClamp : rlb::kEdgeHalo;
+      }
+      segs.push_back(g);
+    }
+  }
+  if ((int64_t)segs.size() > h->L.max_segs) return RLB_E_ARG;
+  RLB_HIP(hipMemcpyAsync(h->d_segs, segs.data(), sizeof(rlb::TubeSeg) * segs.size(),
+                         hipMemcpyHostToDevice, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  h->nseg = (int)segs.size();
+  h->seg_built = 1000 + tv;
+  return RLB_OK;
+}
+
+// Tube rounds: ceil(n / H) launches chained in a HIP graph, each round
+// reading one buffer and writing the other (pingpong) or always A -> B
+// (trials). *flip tells whether the state changed buffers.
+rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
+                        int diag_every, int64_t step0, bool* flip) {
+  const int tv = tube_index(variant);
+  if (!h->all_tubes) return RLB_E_UNSUPPORTED;
+  if (h->seg_built != 1000 + tv) {
+    rlb_status st = build_tube_segments(h, tv);
+    if (st != RLB_OK) return st;
+  }
+  const rlb::TubeVariant v = rlb::tube_variant(tv);
+  const void* func;
+  dim3 block;
+  RLB_HIP(rlb::tube_kernel(h->precision, tv, &func, &block));
+  const int rounds = (nsteps + v.halo - 1) / v.halo;
+  if (h->tgexec) {  // the previous chain may still run: let it finish first
+    RLB_HIP(hipStreamSynchronize(h->stream));
+    (void)hipGraphExecDestroy(h->tgexec);
+    (void)hipGraphDestroy(h->tgraph);
+    h->tgexec = nullptr;
+    h->tgraph = nullptr;
+  }
+  RLB_HIP(hipGraphCreate(&h->tgraph, 0));
+  hipGraphNode_t prev = nullptr;
+  for (int r = 0; r < rounds; ++r) {
+    rlb::TubeRound arg{};
+    const bool odd = pingpong && (r & 1);
+    arg.descs = h->d_descs;
+    arg.segs = (const rlb::TubeSeg*)h->d_segs;
+    arg.src = odd ? b : a;
+    arg.dst = odd ? a : b;
+    arg.cs = h->L.cs;
+    arg.nsteps = std::min(v.halo, nsteps - r * v.halo);
+    arg.diag_every = diag_every;
+    arg.step0 = step0 + (int64_t)r * v.halo;
+    arg.last_step = step0 + nsteps;
+    arg.partials = h->d_partials;
+    arg.bad = h->d_bad;
+    void* args[] = {&arg};
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(func);
+    kp.gridDim = dim3(h->nseg, 1, 1);
+    kp.blockDim = block;
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    RLB_HIP(hipGraphAddKernelNode(&node, h->tgraph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    prev = node;
+  }
+  RLB_HIP(hipGraphInstantiate(&h->tgexec, h->tgraph, nullptr, nullptr, 0));
+  RLB_HIP(hipGraphLaunch(h->tgexec, h->stream));
+  *flip = pingpong && (rounds & 1);
+  return RLB_OK;
 }
 
 // Cut every member into segments of whole z-planes of about nt * cpt cells
@@ -258,7 +370,10 @@ rlb_status segments_fit(rlb_sim* h, int sv, const void* func, int nt) {
 // Persistent kernels run from a one-node HIP graph (built on first use, and
 // again when the kernel changes; later calls only update the arguments).
 rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
-                             int diag_every, int64_t step0) {
+                             int diag_every, int64_t step0, bool* flip) {
+  if (is_tube_variant(h, variant))
+    return launch_tubes(h, variant, nsteps, pingpong, a, b, diag_every, step0, flip);
+  *flip = pingpong && (nsteps & 1);
   const void* func;
   dim3 block, grid;
   void* args[1];
@@ -309,6 +424,7 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
   kp.kernelParams = args;
   kp.extra = nullptr;
   if (h->gexec && h->graph_func != func) {
+    RLB_HIP(hipStreamSynchronize(h->stream));
     (void)hipGraphExecDestroy(h->gexec);
     (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
@@ -346,14 +462,17 @@ rlb_status advance(rlb_sim* h, int32_t n) {
     }
     return RLB_OK;
   }
-  rlb_status st = launch_persistent(h, h->variant, n, 1, state_buf(h), spare_buf(h), D, h->steps);
+  bool flip = false;
+  rlb_status st =
+      launch_persistent(h, h->variant, n, 1, state_buf(h), spare_buf(h), D, h->steps, &flip);
   if (st != RLB_OK) return st;
   if (D > 0) {
     h->diag_step = h->steps + n;
-    h->diag_parts = is_segment_variant(h, h->variant) ? h->nseg : h->n_members;
+    const bool by_seg = is_segment_variant(h, h->variant) || is_tube_variant(h, h->variant);
+    h->diag_parts = by_seg ? h->nseg : h->n_members;
   }
   h->steps += n;
-  if (n & 1) h->cur = 1 - h->cur;
+  if (flip) h->cur = 1 - h->cur;
   return RLB_OK;
 }
 
@@ -395,7 +514,9 @@ namespace {
 const char* kernel_name_of(const rlb_sim* h, int v) {
   if (h->lattice) return rlb::lattice_kernel_name(h->precision, v);
   if (v < rlb::num_member_variants()) return rlb::member_kernel_name(h->precision, v);
-  return rlb::segment_kernel_name(h->precision, v - rlb::num_member_variants());
+  if (is_segment_variant(h, v))
+    return rlb::segment_kernel_name(h->precision, v - rlb::num_member_variants());
+  return rlb::tube_kernel_name(h->precision, tube_index(v));
 }
 
 // A persistent segment launch whose neighbour wait timed out leaves a sticky
@@ -478,6 +599,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->d_error = (int*)(h->d_small + 24);
   h->lattice = lattice_path(n_members, L.ncells);
   h->variant = h->lattice ? 3 : 2;
+  h->all_tubes = true;
+  for (int i = 0; i < n_members; ++i)
+    if (members[i].nx != 1 || members[i].ny != 1) h->all_tubes = false;
 
   auto fail = [&](rlb_status s) {
     delete h;
@@ -708,7 +832,8 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
 rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
   if (!h || !count) return RLB_E_ARG;
   *count = h->lattice ? rlb::num_lattice_variants()
-                      : rlb::num_member_variants() + rlb::num_segment_variants();
+                      : rlb::num_member_variants() + rlb::num_segment_variants() +
+                            rlb::num_tube_variants();
   return RLB_OK;
 }
 
@@ -760,7 +885,8 @@ rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
         for (int i = 0; i < trial_steps && st == RLB_OK; ++i)
           st = launch_lattice_step(h, v, false, state_buf(h), spare_buf(h));
       } else if (st == RLB_OK) {
-        st = launch_persistent(h, v, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0);
+        bool flip = false;
+        st = launch_persistent(h, v, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0, &flip);
         if (st == RLB_E_UNSUPPORTED) {  // segments do not all fit at once
           usable = false;
           st = RLB_OK;
@@ -805,6 +931,8 @@ void rlb_free(rlb_handle h) {
     (void)hipStreamSynchronize(h->stream);
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->tgexec) (void)hipGraphExecDestroy(h->tgexec);
+    if (h->tgraph) (void)hipGraphDestroy(h->tgraph);
     rlb::tape_release(h->tape);
   }
   delete h;

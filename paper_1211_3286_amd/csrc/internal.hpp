@@ -100,6 +100,40 @@ struct SegLaunch {
   double* partials;
   unsigned long long* bad;
 };
+// Quasi-1D members (1 x 1 x L tubes) by rounds of LDS-resident steps: a block
+// owns cells [own0, own1) of one tube and loads the window [win0, win0 + wlen)
+// (the owned cells plus up to H halo cells per side); after h <= H steps in
+// LDS the owned cells are exact and written back. Window edges are either a
+// halo (validity shrinks by one cell per step), the tube's zero-gradient end,
+// or a wrap when the window holds a whole periodic tube.
+enum : int32_t { kEdgeHalo = 0, kEdgeClamp = 1, kEdgeWrap = 2 };
+struct TubeSeg {
+  int32_t member;
+  int32_t own0, own1;
+  int32_t win0, wlen;
+  int32_t left, right;  // edge kinds
+};
+struct TubeRound {
+  const MemberDesc* descs;
+  const TubeSeg* segs;
+  const void* src;
+  void* dst;
+  int64_t cs;
+  int32_t nsteps;  // steps of this round (<= H)
+  int32_t diag_every;
+  int64_t step0;      // global index of the step before this round's first
+  int64_t last_step;  // global index of the last step of the rlb_step call
+  double* partials;
+  unsigned long long* bad;
+};
+struct TubeVariant {
+  int nt, halo;
+};
+int num_tube_variants();
+TubeVariant tube_variant(int i);
+hipError_t tube_kernel(int precision, int variant, const void** func, dim3* block);
+const char* tube_kernel_name(int precision, int variant);
+
 int num_segment_variants();
 MemberVariant segment_variant(int i);  // (threads per block, cells per thread)
 hipError_t segment_kernel(int precision, int variant, const void** func, dim3* block);

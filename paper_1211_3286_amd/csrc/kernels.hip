@@ -234,6 +234,89 @@ __global__ __launch_bounds__(NT) void k_step_segments(SegLaunch a) {
   if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
 }
 
+// -------------------------------------------------------------------------
+// Tube rounds: one block per TubeSeg, one thread per window cell, all
+// populations of the window in LDS as [38][NT] (consecutive threads touch
+// consecutive words). Per step: every thread pulls its 38 values from the
+// LDS neighbours (a 1 x 1 x L lattice streams only along z: the x and y
+// components of e wrap onto the same cell), barrier, collides in registers,
+// writes them back to its own slot, barrier. Inadmissible counts and
+// diagnostics cover owned cells only (halo cells are computed twice).
+// -------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_step_tubes(TubeRound a) {
+  __shared__ T lds[38][NT];
+  const TubeSeg sg = a.segs[blockIdx.x];
+  const MemberDesc d = a.descs[sg.member];
+  const int w = threadIdx.x;
+  const int L = d.nz;
+  const bool live = w < sg.wlen;
+  const int own_lo = sg.own0 - sg.win0, own_hi = sg.own1 - sg.win0;
+  const bool owned = w >= own_lo && w < own_hi;
+  // global cell of window cell w
+  int z = sg.win0 + w;
+  if (z < 0) z += L;
+  if (z >= L) z -= L;
+  const int64_t gi = d.offset + z;
+  if (live) {
+#pragma unroll
+    for (int p = 0; p < 38; ++p) lds[p][w] = ((const T*)a.src)[p * a.cs + gi];
+  }
+  // pull sources inside the window for e_z = +1 (from w-1) and e_z = -1 (from w+1)
+  int sp = w - 1, sm = w + 1;
+  if (sp < 0) sp = sg.left == kEdgeWrap ? sg.wlen - 1 : 0;
+  if (sm >= sg.wlen) sm = sg.right == kEdgeWrap ? 0 : sg.wlen - 1;
+  if (!live) sp = sm = 0;
+  __syncthreads();
+  int nbad = 0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < a.nsteps; ++t) {
+    T f[19], g[19];
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int src = ez(q) > 0 ? sp : (ez(q) < 0 ? sm : w);
+        f[q] = lds[q][src];
+        g[q] = lds[19 + q][src];
+      }
+    }
+    __syncthreads();
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag =
+        a.diag_every > 0 && ((sidx % a.diag_every) == 0 || sidx == a.last_step);
+    if (live) {
+      Sums s;
+      const bool ok = collide<T>(f, g, d.rt, d.ref, s);
+      if (owned) {
+        nbad += ok ? 0 : 1;
+        if (diag)
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] = s.v[i];
+      }
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        lds[q][w] = f[q];
+        lds[19 + q][w] = g[q];
+      }
+    }
+    if (diag) {
+      if (!owned)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] = 0.0;
+      block_sum5<NT>(acc, w);
+      if (w == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
+    }
+    __syncthreads();
+  }
+  if (owned) {
+#pragma unroll
+    for (int p = 0; p < 38; ++p) ((T*)a.dst)[p * a.cs + gi] = lds[p][w];
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
 __device__ __forceinline__ int find_member(const MemberDesc* __restrict__ d, int n, int64_t c) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -406,6 +489,21 @@ const void* seg_func(int v) {
   return nullptr;
 }
 
+constexpr TubeVariant kTube[] = {{256, 8}, {256, 16}, {512, 16}, {512, 32}, {128, 8}};
+constexpr int kNumTube = sizeof(kTube) / sizeof(kTube[0]);
+
+template <typename T>
+const void* tube_func(int v) {
+  switch (v) {
+    case 0: return (const void*)&k_step_tubes<T, 256>;
+    case 1: return (const void*)&k_step_tubes<T, 256>;
+    case 2: return (const void*)&k_step_tubes<T, 512>;
+    case 3: return (const void*)&k_step_tubes<T, 512>;
+    case 4: return (const void*)&k_step_tubes<T, 128>;
+  }
+  return nullptr;
+}
+
 int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -460,6 +558,26 @@ const void* mem_func(int v) {
 
 int num_lattice_variants() { return kNumLat; }
 int num_segment_variants() { return kNumSeg; }
+int num_tube_variants() { return kNumTube; }
+TubeVariant tube_variant(int i) { return kTube[i]; }
+
+hipError_t tube_kernel(int precision, int v, const void** func, dim3* block) {
+  if (v < 0 || v >= kNumTube) return hipErrorInvalidValue;
+  *func = precision ? tube_func<float>(v) : tube_func<double>(v);
+  *block = dim3(kTube[v].nt, 1, 1);
+  return hipSuccess;
+}
+
+const char* tube_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_step_tubes<float,256>/h8", "k_step_tubes<float,256>/h16",
+                              "k_step_tubes<float,512>/h16", "k_step_tubes<float,512>/h32",
+                              "k_step_tubes<float,128>/h8"};
+  static const char* n64[] = {"k_step_tubes<double,256>/h8", "k_step_tubes<double,256>/h16",
+                              "k_step_tubes<double,512>/h16", "k_step_tubes<double,512>/h32",
+                              "k_step_tubes<double,128>/h8"};
+  if (v < 0 || v >= kNumTube) return "?";
+  return precision ? n32[v] : n64[v];
+}
 MemberVariant segment_variant(int i) { return kSeg[i]; }
 
 hipError_t segment_kernel(int precision, int v, const void** func, dim3* block) {

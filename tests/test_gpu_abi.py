@@ -124,7 +124,11 @@ def test_batch_with_one_cell_member_and_segment_diagnostics():
         sim = rlb.from_problems(members, precision=FP64, diag_every=1)
         names = sim.variants()
         sim.variant = v
-        sim.step(5)
+        try:
+            sim.step(5)
+        except rlb.RLBError as e:  # tube rounds need a batch of 1 x 1 x L members
+            assert e.code == -7 and "tubes" in names[v]
+            continue
         sums, step, bad = sim.diagnostics()
         assert step == 5 and bad == 0
         if ref_sums is None:
