@@ -62,10 +62,26 @@ __device__ __forceinline__ int preimages(int c, int e, int N, int bc, int (&out)
 }
 
 // Transposed streaming: adjoint of the pre-collision populations of the cells
-// that pulled population a from cell (x, y, z), summed.
+// that pulled population a from cell (x, y, z), summed. Away from clamped
+// faces that cell is x + e_a, the pull source of the opposite population
+// (e_opp = -e_a), so the gather is 19 plain loads; cells on a clamped face
+// walk the preimage sets per axis.
+__device__ __forceinline__ int opposite(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
+
 template <typename T>
 __device__ __forceinline__ void gather_adjoint(const T* __restrict__ adj, int64_t cs, int x, int y,
                                                int z, const MemberDesc& d, T (&gb)[19]) {
+  const bool face = (d.bcx && (x == 0 || x == d.nx - 1)) ||
+                    (d.bcy && (y == 0 || y == d.ny - 1)) ||
+                    (d.bcz && (z == 0 || z == d.nz - 1));
+  if (!face) {
+    uint32_t off[19], self;
+    pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, (uint32_t)sizeof(T), off,
+                 self);
+#pragma unroll
+    for (int a = 0; a < 19; ++a) gb[a] = ld(adj + (int64_t)a * cs, off[opposite(a)]);
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < 19; ++a) {
     int px[2], py[2], pz[2];
