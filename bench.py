@@ -153,7 +153,7 @@ def bench_blast(torch, rlb, wl, L: int = 512, steps: int = 400, warmup: int = 10
     counted, and the count is reported with the throughput."""
     prob = wl.blast(L)
     sim = rlb.from_problems(prob, precision=rlb.FP32, diag_every=50)
-    tune = sim.tune(trial_steps=2)
+    tune = sim.tune(trial_steps=5)
     del prob
     ms, wall = time_steps(torch, sim, steps, warmup)
     m = sim.moments(allow_unphysical=True)
@@ -164,7 +164,7 @@ def bench_blast(torch, rlb, wl, L: int = 512, steps: int = 400, warmup: int = 10
            "frac": 304 * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
            "inadmissible_cell_updates": m["bad"],
            "inadmissible_fraction": m["bad"] / float(cells * (steps + warmup)),
-           "max_u": float(m["u"].norm(dim=0).max().item()),
+           "max_u_admissible": float(torch.nan_to_num(m["u"].norm(dim=0), nan=0.0).max().item()),
            "workspace_gb": sim.ws_bytes / 1e9}
     sim.close()
     del m
@@ -222,18 +222,43 @@ def cpu_baseline(prob, seconds: float):
 
 
 def summarize_trace(csv_path: str, command: str) -> str:
-    """Markdown table of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    """Markdown tables of a rocprofv3 --kernel-trace --stats run: the
+    kernel_stats.csv summary, and (from the kernel_trace.csv beside it) the
+    step kernels split by launch grid, since one kernel serves several
+    workloads in the default run."""
+    import collections
     import csv
+    import os
+
+    def short(name):
+        name = name.replace("rlb::(anonymous namespace)::", "").replace("void ", "")
+        return name.split("(")[0]
+
     rows = list(csv.DictReader(open(csv_path)))
     out = [f"Command: `{command}`", "",
            "| kernel | calls | average (us) | min (us) | max (us) | total (ms) | % |",
            "|---|---|---|---|---|---|---|"]
     for r in rows:
-        name = r["Name"].replace("rlb::(anonymous namespace)::", "").replace("void ", "")
-        name = name.split("(")[0]
-        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    trace = csv_path.replace("kernel_stats.csv", "kernel_trace.csv")
+    if trace != csv_path and os.path.exists(trace):
+        groups = collections.defaultdict(list)
+        for r in csv.DictReader(open(trace)):
+            name = short(r["Kernel_Name"])
+            if not name.startswith(("k_step", "k_adj_step", "k_gstep")):
+                continue
+            grid = "x".join(r[f"Grid_Size_{a}"] for a in "XYZ")
+            block = "x".join(r[f"Workgroup_Size_{a}"] for a in "XYZ")
+            groups[(name, grid, block)].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        out += ["", "Step kernels by launch grid (threads), from the kernel_trace.csv of the same run:", "",
+                "| kernel | grid | block | launches | average (us) | min (us) | max (us) |",
+                "|---|---|---|---|---|---|---|"]
+        for (name, grid, block), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+            out.append(f"| `{name}` | {grid} | {block} | {len(d)} | {sum(d) / len(d):.1f} | "
+                       f"{min(d):.1f} | {max(d):.1f} |")
     return "\n".join(out) + "\n"
 
 
@@ -299,7 +324,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "slab decomposition is a design, not part of this build", file=sys.stderr)
+              "slab decomposition is a design only; this library runs on one GPU", file=sys.stderr)
         sys.exit(2)
 
     import torch

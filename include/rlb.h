@@ -67,7 +67,8 @@ typedef enum {
   RLB_E_WORKSPACE = -4,   /* workspace NULL, misaligned (needs 256 B) or too small */
   RLB_E_DEVICE = -5,      /* a HIP runtime call failed */
   RLB_E_STATE = -6,       /* call not valid in this state (e.g. rlb_grad without tape) */
-  RLB_E_UNSUPPORTED = -7  /* valid request this build does not provide */
+  RLB_E_UNSUPPORTED = -7  /* valid request the library does not provide (e.g.
+                             tube rounds for a batch that is not all 1 x 1 x L) */
 } rlb_status;
 
 enum { RLB_PERIODIC = 0, RLB_ZERO_GRADIENT = 1 };
