@@ -7,8 +7,10 @@ it, and it never imports the GPU package.
 The arithmetic lives in ``rlb_oracle.cpp`` (built by ``oracle/build.py`` into
 ``oracle/liboracle.so``); this module only marshals numpy arrays.
 
-Layout: populations are ``(19, nz, ny, nx)`` float64 arrays (one for f, one
-for g); fields are ``(nz, ny, nx)`` and velocities ``(3, nz, ny, nx)``.
+Layout: populations are ``(Q, nz, ny, nx)`` float64 arrays (one for f, one
+for g; Q = 19 for D3Q19, 9 for the D2Q9 model of Sec. V.A on nx x ny x 1
+lattices); fields are ``(nz, ny, nx)`` and velocities ``(3, nz, ny, nx)``.
+A problem selects its lattice with ``params.lattice`` ("d3q19" or "d2q9").
 """
 
 from __future__ import annotations
@@ -47,6 +49,15 @@ def _load():
     lib.oracle_tables.argtypes = [I, D, D, D, D]
     lib.oracle_d2q9_tables.argtypes = [I, D, D]
     lib.oracle_d2q9_geq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
+    lib.oracle_d2q9_feq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
+    lib.oracle_d2q9_rates.argtypes = [P, D]
+    lib.oracle_d2q9_collide_cell.argtypes = [P, D, D, D, D]
+    lib.oracle_d2q9_collide_cell.restype = ctypes.c_int
+    lib.oracle_d2q9_init.argtypes = [P, D, D, D, D, D]
+    lib.oracle_d2q9_step.argtypes = [P, ctypes.c_int32, D, D]
+    lib.oracle_d2q9_step.restype = ctypes.c_int64
+    lib.oracle_d2q9_fields.argtypes = [P, D, D, D, D, D, D, D, D]
+    lib.oracle_d2q9_fields.restype = ctypes.c_int64
     lib.oracle_feq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_geq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_recover.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
@@ -72,6 +83,15 @@ def _ptr(a):
         return None
     assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def is_d2q9(p) -> bool:
+    return getattr(p, "lattice", "d3q19") == "d2q9"
+
+
+def nvel(p) -> int:
+    """Number of velocities of the lattice of ``p``."""
+    return 9 if is_d2q9(p) else 19
 
 
 def cparams(p) -> CParams:
@@ -122,6 +142,13 @@ def d2q9_geq(sigma: float, P: float, u) -> np.ndarray:
     return out
 
 
+def d2q9_feq(n: float, gamma: float, u) -> np.ndarray:
+    out = np.zeros(9)
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    _load().oracle_d2q9_feq(float(n), float(gamma), _ptr(uu), _ptr(out))
+    return out
+
+
 def feq(n: float, gamma: float, u) -> np.ndarray:
     out = np.zeros(19)
     uu = np.ascontiguousarray(u, dtype=np.float64)
@@ -145,19 +172,25 @@ def recover(N: float, E: float, M) -> Tuple[bool, Dict[str, float]]:
 
 
 def rates(p) -> np.ndarray:
-    out = np.zeros(19)
+    """Diagonal of S (0 on the conserved rows)."""
+    q = nvel(p)
+    out = np.zeros(q)
     cp = cparams(p)
-    _load().oracle_rates(ctypes.byref(cp), _ptr(out))
+    fn = _load().oracle_d2q9_rates if q == 9 else _load().oracle_rates
+    fn(ctypes.byref(cp), _ptr(out))
     return out
 
 
 def collide_cell(p, f, g):
+    q = nvel(p)
     f = np.ascontiguousarray(f, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
-    fo = np.zeros(19)
-    go = np.zeros(19)
+    assert f.shape == (q,) and g.shape == (q,)
+    fo = np.zeros(q)
+    go = np.zeros(q)
     cp = cparams(p)
-    ok = _load().oracle_collide_cell(ctypes.byref(cp), _ptr(f), _ptr(g), _ptr(fo), _ptr(go))
+    fn = _load().oracle_d2q9_collide_cell if q == 9 else _load().oracle_collide_cell
+    ok = fn(ctypes.byref(cp), _ptr(f), _ptr(g), _ptr(fo), _ptr(go))
     return bool(ok), fo, go
 
 
@@ -174,19 +207,26 @@ class State:
     @classmethod
     def init(cls, problem) -> "State":
         p = problem.params
-        shape = (19, p.nz, p.ny, p.nx)
+        shape = (nvel(p), p.nz, p.ny, p.nx)
         f = np.zeros(shape)
         g = np.zeros(shape)
         cp = cparams(p)
         n0 = np.ascontiguousarray(problem.n, dtype=np.float64)
         e0 = np.ascontiguousarray(problem.eps, dtype=np.float64)
         u0 = np.ascontiguousarray(problem.u, dtype=np.float64)
-        _load().oracle_init(ctypes.byref(cp), _ptr(n0), _ptr(e0), _ptr(u0), _ptr(f), _ptr(g))
+        if is_d2q9(p):
+            if p.nz != 1 or np.any(u0[2] != 0.0):
+                raise ValueError("a D2Q9 lattice is nx x ny x 1 with u_z = 0")
+            fn = _load().oracle_d2q9_init
+        else:
+            fn = _load().oracle_init
+        fn(ctypes.byref(cp), _ptr(n0), _ptr(e0), _ptr(u0), _ptr(f), _ptr(g))
         return cls(p, f, g)
 
     def step(self, nsteps: int = 1) -> int:
         cp = cparams(self.params)
-        bad = _load().oracle_step(ctypes.byref(cp), int(nsteps), _ptr(self.f), _ptr(self.g))
+        fn = _load().oracle_d2q9_step if is_d2q9(self.params) else _load().oracle_step
+        bad = fn(ctypes.byref(cp), int(nsteps), _ptr(self.f), _ptr(self.g))
         self.t += nsteps
         self.bad += int(bad)
         return int(bad)
@@ -202,8 +242,9 @@ class State:
         u = np.zeros((3,) + shape)
         sums = np.zeros(5)
         cp = cparams(p)
-        bad = _load().oracle_fields(ctypes.byref(cp), _ptr(self.f), _ptr(self.g), _ptr(n),
-                                    _ptr(eps), _ptr(P), _ptr(gam), _ptr(u), _ptr(sums))
+        fn = _load().oracle_d2q9_fields if is_d2q9(p) else _load().oracle_fields
+        bad = fn(ctypes.byref(cp), _ptr(self.f), _ptr(self.g), _ptr(n), _ptr(eps), _ptr(P),
+                 _ptr(gam), _ptr(u), _ptr(sums))
         return {"n": n, "eps": eps, "P": P, "gamma": gam, "u": u, "sums": sums,
                 "bad": int(bad)}
 
@@ -216,8 +257,10 @@ def run(problem, nsteps: int) -> State:
 
 
 def grad(problem, nsteps: int, dL_du: np.ndarray, dL_deps: np.ndarray):
-    """FP64 adjoint: (dL/d(tau_v, tau_e, tau_eps), dL/deps0, dL/du0)."""
+    """FP64 adjoint: (dL/d(tau_v, tau_e, tau_eps), dL/deps0, dL/du0). D3Q19 only."""
     p = problem.params
+    if is_d2q9(p):
+        raise ValueError("the adjoint oracle covers the D3Q19 model only")
     shape = (p.nz, p.ny, p.nx)
     dtau = np.zeros(3)
     de0 = np.zeros(shape)

@@ -23,6 +23,10 @@
 //     written as a pull with periodic wrap or zero-gradient clamp per axis.
 //   * Adjoint of the g update (recovery, equilibria, MRT, streaming) by
 //     complex-step Jacobians of the very same per-cell code.
+//   * The D2Q9 MRT model the paper itself runs (Sec. V.A, Eqs. 30-35): its
+//     own velocity set, weights, basis (the rows that reproduce Eq. 34),
+//     S of Eq. (31), g_eq of Eqs. (32)-(33), f_eq of Eq. (7)'s form with the
+//     D2Q9 weights, the same recovery, on an nx x ny x 1 lattice.
 //
 // Readings where the paper is silent are listed in the design notes; each one
 // used here is named at its place in the code.
@@ -312,6 +316,140 @@ inline int64_t src_cell(const Params& p, int x, int y, int z, int a) {
 
 double tau_q_of(const Params& p) { return p.tau_q > 0.0 ? p.tau_q : p.tau_v; }
 
+// ---------------------------------------------------------------------------
+// D2Q9 lattice of Sec. V.A. Velocities: rest, (1,0), (0,1), (-1,0), (0,-1),
+// (1,1), (-1,1), (-1,-1), (1,-1) in the (x, y) plane of an nx x ny x 1
+// lattice; weights 4/9, 1/9, 1/36 (c_s^2 = 1/3). The moment basis is the
+// orthogonal D2Q9 basis the paper takes from its Ref. [24]; restricted to
+// g_eq of Eqs. (32)-(33) it gives the printed m_eq of Eq. (34), a property
+// the tests check. Row order: rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy.
+// ---------------------------------------------------------------------------
+const int EV2[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
+                       {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+double WV2[9];
+double MM2[9][9];
+double MINV2[9][9];
+bool tables2_ready = false;
+
+double basis_poly2(int k, double x, double y) {
+  double r2 = x * x + y * y;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return 3.0 * r2 - 4.0;
+    case 2: return (9.0 * r2 * r2 - 21.0 * r2 + 8.0) / 2.0;
+    case 3: return x;
+    case 4: return (3.0 * r2 - 5.0) * x;
+    case 5: return y;
+    case 6: return (3.0 * r2 - 5.0) * y;
+    case 7: return x * x - y * y;
+    case 8: return x * y;
+  }
+  return 0.0;
+}
+
+void build_tables2() {
+  if (tables2_ready) return;
+  for (int a = 0; a < 9; ++a) {
+    int r2 = EV2[a][0] * EV2[a][0] + EV2[a][1] * EV2[a][1];
+    WV2[a] = (r2 == 0) ? 4.0 / 9.0 : (r2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+    for (int k = 0; k < 9; ++k) MM2[k][a] = basis_poly2(k, EV2[a][0], EV2[a][1]);
+  }
+  invert(9, &MM2[0][0], &MINV2[0][0]);
+  tables2_ready = true;
+}
+
+// Rows of the D2Q9 basis that carry conserved quantities: rho and j.
+inline bool conserved_row2(int k) { return k == 0 || k == 3 || k == 5; }
+
+// Diagonal of S, Eq. (31): (1/tau_sigma, 1/tau_e, 1/tau_eps, 1/tau_j, 1/tau_q,
+// 1/tau_j, 1/tau_q, 1/tau_v, 1/tau_v). The conserved rows (tau_sigma = tau_j =
+// dt) have their deviation set to zero in collide_g2, so their entry is not
+// used; it is stored as 0. tau_q <= 0 means tau_q = tau_v.
+void rates2(const Params& p, double s[9]) {
+  const double tq = p.tau_q > 0.0 ? p.tau_q : p.tau_v;
+  s[0] = s[3] = s[5] = 0.0;
+  s[1] = 1.0 / p.tau_e;
+  s[2] = 1.0 / p.tau_eps;
+  s[4] = s[6] = 1.0 / tq;
+  s[7] = s[8] = 1.0 / p.tau_v;
+}
+
+// f_eq with the form of Eq. (7) and the D2Q9 weights (reading: f lives on
+// the same lattice as g and keeps its BGK collision, Eq. 5).
+void f_equilibrium2(double n_gamma, const double u[2], double feq[9]) {
+  double uu = u[0] * u[0] + u[1] * u[1];
+  for (int a = 0; a < 9; ++a) {
+    double eu = EV2[a][0] * u[0] + EV2[a][1] * u[1];
+    feq[a] = WV2[a] * n_gamma *
+             (1.0 + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+// g_eq of Eqs. (32)-(33), sigma = (eps + P) gamma^2.
+void g_equilibrium2(double sigma, double P, const double u[2], double geq[9]) {
+  double uu = u[0] * u[0] + u[1] * u[1];
+  geq[0] = WV2[0] * sigma *
+           (9.0 / 4.0 - P * (5.0 + 9.0 * CS2) / (4.0 * sigma * CS2) - uu / (2.0 * CS2));
+  for (int a = 1; a < 9; ++a) {
+    double eu = EV2[a][0] * u[0] + EV2[a][1] * u[1];
+    geq[a] = WV2[a] * sigma *
+             (P / (sigma * CS2) + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+}
+
+// Eq. (10) sums of a D2Q9 cell; M[2] = 0 (no z velocity).
+void moments2(const double f[9], const double g[9], double& N, double& E, double M[3]) {
+  N = E = 0.0;
+  M[0] = M[1] = M[2] = 0.0;
+  for (int a = 0; a < 9; ++a) {
+    N += f[a];
+    E += g[a];
+    M[0] += EV2[a][0] * g[a];
+    M[1] += EV2[a][1] * g[a];
+  }
+}
+
+// One D2Q9 cell: recovery (same root as D3Q19, Eq. 10 with P = eps/3), f BGK
+// (Eq. 5), g MRT (Eq. 35): m = M g, m_eq = M g_eq, m* = m - S (m - m_eq),
+// g* = M^-1 m*. Returns false (and copies) when the cell is inadmissible.
+bool cell2(const Params& p, const double s[9], const double f[9], const double g[9],
+           double fout[9], double gout[9]) {
+  double N, E, M[3];
+  moments2(f, g, N, E, M);
+  Fields<double> F;
+  if (!recover<double>(N, E, M, F)) {
+    for (int a = 0; a < 9; ++a) {
+      fout[a] = f[a];
+      gout[a] = g[a];
+    }
+    return false;
+  }
+  double feq[9], geq[9], m[9], meq[9], ms[9];
+  f_equilibrium2(F.n * F.gamma, F.u, feq);
+  for (int a = 0; a < 9; ++a) fout[a] = f[a] - (f[a] - feq[a]) / p.tau_f;
+  g_equilibrium2(F.sigma, F.P, F.u, geq);
+  for (int k = 0; k < 9; ++k) {
+    m[k] = meq[k] = 0.0;
+    for (int a = 0; a < 9; ++a) {
+      m[k] += MM2[k][a] * g[a];
+      meq[k] += MM2[k][a] * geq[a];
+    }
+    double d = conserved_row2(k) ? 0.0 : (m[k] - meq[k]);
+    ms[k] = m[k] - s[k] * d;
+  }
+  for (int a = 0; a < 9; ++a) {
+    gout[a] = 0.0;
+    for (int k = 0; k < 9; ++k) gout[a] += MINV2[a][k] * ms[k];
+  }
+  return true;
+}
+
+inline int64_t src_cell2(const Params& p, int x, int y, int a) {
+  int sx = src_coord(x, EV2[a][0], p.nx, p.bc[0]);
+  int sy = src_coord(y, EV2[a][1], p.ny, p.bc[1]);
+  return (int64_t)sy * p.nx + sx;
+}
+
 int g_threads = 0;
 
 }  // namespace
@@ -352,38 +490,133 @@ void oracle_tables(int* e, double* w, double* M, double* Minv, double* norms) {
   }
 }
 
-// D2Q9 lattice of Sec. V.A (Eqs. 31-34), used to check the moment basis
-// convention against the printed Eq. (34). Velocities: rest, (1,0), (0,1),
-// (-1,0), (0,-1), (1,1), (-1,1), (-1,-1), (1,-1); weights 4/9, 1/9, 1/36.
-// Basis rows: 1, 3r^2-4, (9r^4-21r^2+8)/2, x, (3r^2-5)x, y, (3r^2-5)y,
-// x^2-y^2, xy.
+// D2Q9 velocities (9 x 2), weights and moment basis (row-major 9 x 9).
 void oracle_d2q9_tables(int* e, double* w, double* M) {
-  const int ev[9][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1},
-                        {1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+  build_tables2();
   for (int a = 0; a < 9; ++a) {
-    double x = ev[a][0], y = ev[a][1], r2 = x * x + y * y;
-    e[2 * a] = ev[a][0];
-    e[2 * a + 1] = ev[a][1];
-    w[a] = (r2 == 0) ? 4.0 / 9.0 : (r2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
-    double row[9] = {1.0, 3.0 * r2 - 4.0, (9.0 * r2 * r2 - 21.0 * r2 + 8.0) / 2.0, x,
-                     (3.0 * r2 - 5.0) * x, y, (3.0 * r2 - 5.0) * y, x * x - y * y, x * y};
-    for (int k = 0; k < 9; ++k) M[k * 9 + a] = row[k];
+    e[2 * a] = EV2[a][0];
+    e[2 * a + 1] = EV2[a][1];
+    w[a] = WV2[a];
+    for (int k = 0; k < 9; ++k) M[k * 9 + a] = MM2[k][a];
   }
 }
 
-// D2Q9 g_eq, Eqs. (32)-(33).
+// D2Q9 g_eq, Eqs. (32)-(33); u has 2 components.
 void oracle_d2q9_geq(double sigma, double P, const double* u, double* geq) {
-  int e[18];
-  double w[9], M[81];
-  oracle_d2q9_tables(e, w, M);
-  double uu = u[0] * u[0] + u[1] * u[1];
-  geq[0] = w[0] * sigma *
-           (9.0 / 4.0 - P * (5.0 + 9.0 * CS2) / (4.0 * sigma * CS2) - uu / (2.0 * CS2));
-  for (int a = 1; a < 9; ++a) {
-    double eu = e[2 * a] * u[0] + e[2 * a + 1] * u[1];
-    geq[a] = w[a] * sigma *
-             (P / (sigma * CS2) + eu / CS2 + eu * eu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  build_tables2();
+  g_equilibrium2(sigma, P, u, geq);
+}
+
+// D2Q9 f_eq (Eq. 7's form, D2Q9 weights).
+void oracle_d2q9_feq(double n, double gamma, const double* u, double* feq) {
+  build_tables2();
+  f_equilibrium2(n * gamma, u, feq);
+}
+
+void oracle_d2q9_rates(const Params* p, double* s) { rates2(*p, s); }
+
+// Collision of one D2Q9 cell. Returns 1 if the cell was admissible.
+int oracle_d2q9_collide_cell(const Params* p, const double* f, const double* g, double* fout,
+                             double* gout) {
+  build_tables2();
+  double s[9];
+  rates2(*p, s);
+  return cell2(*p, s, f, g, fout, gout) ? 1 : 0;
+}
+
+// D2Q9 state at t = 0 on an nx x ny x 1 lattice: f = f_eq(n0, u0),
+// g = g_eq(eps0, eps0/3, u0). u0 has 3 planes; the third must be zero.
+void oracle_d2q9_init(const Params* p, const double* n0, const double* eps0, const double* u0,
+                      double* f, double* g) {
+  build_tables2();
+  const int64_t nc = (int64_t)p->nx * p->ny;
+  for (int64_t c = 0; c < nc; ++c) {
+    double u[2] = {u0[c], u0[nc + c]};
+    double uu = u[0] * u[0] + u[1] * u[1];
+    double gamma = 1.0 / std::sqrt(1.0 - uu);
+    double P = eps0[c] / 3.0;
+    double sigma = (eps0[c] + P) * gamma * gamma;
+    double fe[9], ge[9];
+    f_equilibrium2(n0[c] * gamma, u, fe);
+    g_equilibrium2(sigma, P, u, ge);
+    for (int a = 0; a < 9; ++a) {
+      f[a * nc + c] = fe[a];
+      g[a * nc + c] = ge[a];
+    }
   }
+}
+
+// nsteps D2Q9 time steps in place: pull, sums, recovery, collisions.
+// Returns the number of inadmissible cell-updates.
+int64_t oracle_d2q9_step(const Params* p, int32_t nsteps, double* f, double* g) {
+  build_tables2();
+  const int64_t nc = (int64_t)p->nx * p->ny;
+  double s[9];
+  rates2(*p, s);
+  std::vector<double> fn((size_t)(9 * nc)), gn((size_t)(9 * nc));
+  int64_t bad = 0;
+  for (int t = 0; t < nsteps; ++t) {
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int64_t c = (int64_t)y * p->nx + x;
+        double fl[9], gl[9], fo[9], go[9];
+        for (int a = 0; a < 9; ++a) {
+          int64_t sc = src_cell2(*p, x, y, a);
+          fl[a] = f[a * nc + sc];
+          gl[a] = g[a * nc + sc];
+        }
+        if (!cell2(*p, s, fl, gl, fo, go)) ++bad;
+        for (int a = 0; a < 9; ++a) {
+          fn[a * nc + c] = fo[a];
+          gn[a * nc + c] = go[a];
+        }
+      }
+    std::memcpy(f, fn.data(), sizeof(double) * 9 * nc);
+    std::memcpy(g, gn.data(), sizeof(double) * 9 * nc);
+  }
+  return bad;
+}
+
+// Fields of a stored D2Q9 state (u has 3 planes, the third is 0) and the
+// lattice sums {N, E, Mx, My, 0}. Returns the number of inadmissible cells.
+int64_t oracle_d2q9_fields(const Params* p, const double* f, const double* g, double* n,
+                           double* eps, double* P, double* gamma, double* u, double* sums) {
+  build_tables2();
+  const int64_t nc = (int64_t)p->nx * p->ny;
+  int64_t bad = 0;
+  double S[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = 0; c < nc; ++c) {
+    double fl[9], gl[9];
+    for (int a = 0; a < 9; ++a) {
+      fl[a] = f[a * nc + c];
+      gl[a] = g[a * nc + c];
+    }
+    double N, E, M[3];
+    moments2(fl, gl, N, E, M);
+    S[0] += N;
+    S[1] += E;
+    S[2] += M[0];
+    S[3] += M[1];
+    Fields<double> F;
+    if (!recover<double>(N, E, M, F)) {
+      ++bad;
+      double q = std::nan("");
+      F.n = F.eps = F.P = F.gamma = F.u[0] = F.u[1] = F.u[2] = q;
+    }
+    if (n) n[c] = F.n;
+    if (eps) eps[c] = F.eps;
+    if (P) P[c] = F.P;
+    if (gamma) gamma[c] = F.gamma;
+    if (u) {
+      u[c] = F.u[0];
+      u[nc + c] = F.u[1];
+      u[2 * nc + c] = F.u[2];
+    }
+  }
+  if (sums)
+    for (int k = 0; k < 5; ++k) sums[k] = S[k];
+  return bad;
 }
 
 void oracle_feq(double n, double gamma, const double* u, double* feq) {

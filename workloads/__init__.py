@@ -22,6 +22,7 @@ problem class the model was built for):
 ``tube_batch``     64 ragged shock tubes with per-tube relaxation times.
 ``shear_vortex``   2D periodic shear wave + Taylor-Green vortex (adjoint).
 ``blast``          3D spherical blast with an outward velocity shell.
+``qgp_tube_2d``    the 4 x 800 D2Q9 shock tube of Sec. V.B, Cases A-D.
 """
 
 from __future__ import annotations
@@ -49,6 +50,7 @@ class Params:
     tau_e: float = 0.9
     tau_eps: float = 0.9
     tau_q: float = 0.0  # <= 0: ghost moments relax with tau_v
+    lattice: str = "d3q19"  # or "d2q9" (nx x ny x 1, velocities in the x-y plane)
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -272,6 +274,60 @@ def blast(L: int = 512, radius: float | None = None, shell: float | None = None,
     return Problem(prm, n, 3.0 * P, u, name=f"blast_{L}x{L}x{L}")
 
 
+# Initial states of the quark-gluon-plasma shock tubes in lattice units
+# (Sec. III.B and the moderately relativistic case of Sec. V.B): pressure
+# left / right of the membrane and temperature left / right; n = P / T.
+QGP_WEAK = {"P_L": 2.495e-7, "P_R": 1.023e-7, "T_L": 0.0314, "T_R": 0.0314}
+QGP_MODERATE = {"P_L": 2.495e-7, "P_R": 1.557e-8, "T_L": 0.0359, "T_R": 0.018}
+
+
+def case_taus(case: str, tau_v: float, a: float) -> Dict[str, float]:
+    """Relaxation times of the four MRT cases of Sec. V.B, with
+    tau_x - 1/2 = a (tau_v - 1/2) for the reduced ones:
+    A: tau_e = tau_eps = tau_q = tau_v;  B: tau_q reduced;
+    C: tau_e reduced;                    D: tau_e and tau_eps reduced."""
+    red = 0.5 + a * (tau_v - 0.5)
+    t = {"tau_v": tau_v, "tau_e": tau_v, "tau_eps": tau_v, "tau_q": tau_v}
+    if case == "B":
+        t["tau_q"] = red
+    elif case == "C":
+        t["tau_e"] = red
+    elif case == "D":
+        t["tau_e"] = red
+        t["tau_eps"] = red
+    elif case != "A":
+        raise ValueError(f"unknown case {case!r}")
+    return t
+
+
+def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
+                tau_f: float = 0.6, nx: int = 4, length: int = 800, moderate: bool = False,
+                width: float = 1.0) -> Problem:
+    """D2Q9 shock tube of Sec. V.B on nx x length x 1 cells.
+
+    x is periodic (nx = 4 cells), the long axis y stands for the paper's z
+    and has zero-gradient ends; the membrane sits between cells length/2 - 1
+    and length/2 (tanh of width ``width``). Weak case: P_L, P_R of Sec. III.B
+    at T = 0.0314; ``moderate``: the moderately relativistic case (P_R =
+    1.557e-8, T_L / T_R = 0.0359 / 0.018). n = P / T, u = 0. Relaxation times
+    from ``case_taus``; tau_v = 100 stands for the paper's "about 100".
+    """
+    st = QGP_MODERATE if moderate else QGP_WEAK
+    y = np.arange(length, dtype=np.float64)
+    P = _tanh_step(y, length / 2.0, width, st["P_L"], st["P_R"])
+    T = _tanh_step(y, length / 2.0, width, st["T_L"], st["T_R"])
+    n = P / T
+    shape = (1, length, nx)
+    t = case_taus(case, tau_v, a)
+    prm = Params(nx, length, 1, (PERIODIC, ZERO_GRADIENT, PERIODIC), tau_f, t["tau_v"],
+                 t["tau_e"], t["tau_eps"], t["tau_q"], "d2q9")
+    ones = np.ones((1, 1, nx))
+    return Problem(prm, (n[None, :, None] * ones).copy(), (3.0 * P[None, :, None] * ones).copy(),
+                   np.zeros((3,) + shape),
+                   name=f"qgp_tube_2d_{nx}x{length}_case{case}" + ("_moderate" if moderate else ""),
+                   meta={"case": case, "a": a})
+
+
 def uniform(nx: int, ny: int, nz: int, n: float = 1.0, eps: float = 1.0,
             u=(0.0, 0.0, 0.0), **tau) -> Problem:
     """A uniform state (every cell identical)."""
@@ -315,7 +371,7 @@ def window(problem: Problem, center: Tuple[int, int, int], half: int):
             sub_bc.append(ZERO_GRADIENT)
     iz, iy, ix = np.ix_(*idx)
     sub = Params(len(idx[2]), len(idx[1]), len(idx[0]), (sub_bc[2], sub_bc[1], sub_bc[0]),
-                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q)
+                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q, prm.lattice)
     u = np.stack([problem.u[c][iz, iy, ix] for c in range(3)])
     return (Problem(sub, problem.n[iz, iy, ix].copy(), problem.eps[iz, iy, ix].copy(), u,
                     name=problem.name + "_window"), tuple(loc))
