@@ -8,8 +8,10 @@ FP32 populations with FP64 recovery and FP64 conservation sums fused into
 every step. One timed step = one fused kernel launch over all 16.8M cells.
 
 Also reported ("forms"): the same step in FP64, the batched persistent
-launch over 64 ragged shock tubes (3000 steps, one graph launch), and the
-adjoint gradient of a 512 x 512 run (1000 steps, checkpoints every 50).
+launch over 64 ragged shock tubes (3000 steps, one graph launch), the
+adjoint gradient of a 512 x 512 run (1000 steps, checkpoints every 50), the
+512^3 blast, and the D2Q9 MRT model of Sec. V (a 4096^2 lattice and the
+4 x 800 Cases A-D batch).
 
 Prints one JSON line. ``value`` is MLUPS (million lattice-cell updates per
 second) with the populations resident in HBM; ``roofline`` prices the fused
@@ -203,6 +205,50 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50):
             "dL_dtau": [float(x) for x in dtau]}
 
 
+def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10):
+    """The D2Q9 MRT model of Sec. V.A: an n x n periodic random flow in FP32
+    and FP64 (one fused launch per step, 2 x 18 populations per cell update),
+    and the four Sec. V.B cases on 4 x 800 as one persistent batch, 400 steps."""
+    prob = wl.random_modes(n, n, 1, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    prob.params.lattice = "d2q9"
+    cells = prob.params.ncells
+    out = {"lattice": f"{n}x{n}x1 periodic", "steps": steps}
+    for prec, name in ((rlb.FP32, "fp32"), (rlb.FP64, "fp64")):
+        sim = rlb.from_problems(prob, precision=prec, diag_every=50)
+        tune = sim.tune(trial_steps=3)
+        s0 = sim.sums()
+        ms, _ = time_steps(torch, sim, steps, warmup)
+        s1 = sim.sums()
+        bpc = 2 * 18 * (4 if prec == rlb.FP32 else 8)
+        gbs = bpc * cells / (ms * 1e-3) / 1e9
+        out[name] = {"ms_per_step": ms, "mlups": cells / (ms * 1e-3) / 1e6,
+                     "kernel": tune["name"], "bytes_per_cell": bpc, "achieved_gbs": gbs,
+                     "frac": gbs / HBM_PEAK_GBS,
+                     "conservation_drift": float(abs(s1 - s0).max() / abs(s0[:2]).max())}
+        sim.close()
+    del prob
+    cases = [wl.qgp_tube_2d(c) for c in "ABCD"]
+    nc = sum(c.params.ncells for c in cases)
+    for prec, name in ((rlb.FP64, "cases_A_D_fp64"), (rlb.FP32, "cases_A_D_fp32")):
+        sim = rlb.from_problems(cases, precision=prec)
+        tune = sim.tune(trial_steps=50)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(400)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[name] = {"members": "4 x (4x800), Cases A-D, a = 1/20", "steps": 400,
+                     "ms_total": ms, "us_per_step": 1e3 * ms / 400,
+                     "mlups": nc * 400 / (ms * 1e-3) / 1e6, "kernel": tune["name"],
+                     "inadmissible": sim.moments()["bad"]}
+        sim.close()
+    return out
+
+
 def cpu_baseline(prob, seconds: float):
     """The FP64 oracle on the host cores, on whole steps of the same lattice."""
     import oracle
@@ -360,6 +406,8 @@ def main():
         log("adjoint", forms["adjoint"])
         forms["blast_512"] = bench_blast(torch, rlb, wl)
         log("blast", forms["blast_512"])
+        forms["d2q9"] = bench_d2q9(torch, rlb, wl)
+        log("d2q9", forms["d2q9"])
     if args.copy_calibration:
         forms["copy_calibration"] = copy_calibration(torch)
         log("copy", forms["copy_calibration"])

@@ -24,6 +24,16 @@
  *  11: (+1,0,+1) 12: (-1,0,-1) 13: (+1,0,-1) 14: (-1,0,+1)
  *  15: (0,+1,+1) 16: (0,-1,-1) 17: (0,+1,-1) 18: (0,-1,+1)
  *
+ * The D2Q9 model (rlb_options.lattice = RLB_D2Q9) is the MRT model the paper
+ * runs in Sec. V (Eqs. 30-35): S = diag(1/tau_sigma, 1/tau_e, 1/tau_eps,
+ * 1/tau_j, 1/tau_q, 1/tau_j, 1/tau_q, 1/tau_v, 1/tau_v) (Eq. 31), g_eq of
+ * Eqs. (32)-(33), moment equilibria Eq. (34); f keeps the BGK of Eq. (5) with
+ * f_eq of Eq. (7)'s form and the D2Q9 weights 4/9, 1/9, 1/36. Its lattices
+ * are nx x ny x 1 (velocities in the x-y plane, u_z = 0); velocity order:
+ *   0: (0,0)  1: (+1,0)  2: (0,+1)  3: (-1,0)  4: (0,-1)
+ *   5: (+1,+1)  6: (-1,+1)  7: (-1,-1)  8: (+1,-1)
+ * and every "19" below reads 9 for it.
+ *
  * Field layout: a lattice of nx*ny*nz cells, x fastest: cell = x + nx*(y + ny*z).
  * A batch of members ("n_members" lattices, e.g. shock tubes of uneven
  * length) is packed member after member; member m starts at the prefix sum of
@@ -73,6 +83,7 @@ typedef enum {
 
 enum { RLB_PERIODIC = 0, RLB_ZERO_GRADIENT = 1 };
 enum { RLB_FP64 = 0, RLB_FP32 = 1 };
+enum { RLB_D3Q19 = 0, RLB_D2Q9 = 1 };
 
 /* One lattice (or one member of a batch). */
 typedef struct {
@@ -84,7 +95,8 @@ typedef struct {
   double tau_v;        /* shear rows (3p_xx, p_ww, p_xy, p_yz, p_xz), Eq. (31) */
   double tau_e;        /* energy row e (bulk viscosity), Eq. (31) */
   double tau_eps;      /* energy-square row eps, Eq. (31) */
-  double tau_q;        /* ghost rows (q, 3pi_xx, pi_ww, m); <= 0 means tau_q = tau_v */
+  double tau_q;        /* ghost rows (q, 3pi_xx, pi_ww, m; D2Q9: the q rows of
+                          Eq. 31); <= 0 means tau_q = tau_v */
 } rlb_params;
 
 typedef struct {
@@ -98,6 +110,10 @@ typedef struct {
   int32_t diag_every;  /* 0: none. D > 0: every D-th step (and the last step of each
                           rlb_step call) also leaves per-block FP64 partial sums of
                           the conservation moments, read by rlb_diagnostics. */
+  int32_t lattice;     /* RLB_D3Q19 (0) or RLB_D2Q9 (1). D2Q9: every member has
+                          nz = 1 and every input cell u_z = 0 (else RLB_E_ARG,
+                          RLB_E_UNPHYSICAL); no tape (ckpt_every > 0 gives
+                          RLB_E_UNSUPPORTED). */
 } rlb_options;
 
 typedef struct rlb_sim* rlb_handle;

@@ -8,7 +8,9 @@ built library or a GPU, constructing a :class:`Simulation` raises.
 
 Layout conventions (same as the C ABI): a lattice of nx*ny*nz cells is
 C-ordered ``(nz, ny, nx)``; velocities are ``(3, nz, ny, nx)``; a batch of
-members is packed member after member along one flat cell axis.
+members is packed member after member along one flat cell axis. Two lattice
+models: D3Q19 (default) and the D2Q9 MRT model of Sec. V.A
+(``lattice=D2Q9``, nx x ny x 1 lattices with u_z = 0).
 """
 
 from __future__ import annotations
@@ -28,6 +30,8 @@ STATUS = {0: "RLB_OK", -1: "RLB_E_ARG", -2: "RLB_E_TAU", -3: "RLB_E_UNPHYSICAL",
           -4: "RLB_E_WORKSPACE", -5: "RLB_E_DEVICE", -6: "RLB_E_STATE", -7: "RLB_E_UNSUPPORTED"}
 FP64, FP32 = 0, 1
 PERIODIC, ZERO_GRADIENT = 0, 1
+D3Q19, D2Q9 = 0, 1
+LATTICE_NAMES = {"d3q19": D3Q19, "d2q9": D2Q9}
 
 # Entry points declared in include/rlb.h (checked against the header by the tests).
 ENTRY_POINTS = ["rlb_workspace_size", "rlb_init", "rlb_step", "rlb_moments", "rlb_diagnostics",
@@ -51,7 +55,8 @@ class CParams(ctypes.Structure):
 
 class COptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
-                ("tape_steps", ctypes.c_int32), ("diag_every", ctypes.c_int32)]
+                ("tape_steps", ctypes.c_int32), ("diag_every", ctypes.c_int32),
+                ("lattice", ctypes.c_int32)]
 
 
 _lib = None
@@ -121,9 +126,17 @@ def cparams(members: Sequence) -> ctypes.Array:
     return arr
 
 
+def lattice_code(lattice) -> int:
+    """D3Q19 / D2Q9 from an int or a name ("d3q19", "d2q9")."""
+    if isinstance(lattice, str):
+        return LATTICE_NAMES[lattice.lower()]
+    return int(lattice)
+
+
 def options(precision: int = FP32, ckpt_every: int = 0, tape_steps: int = 0,
-            diag_every: int = 0) -> COptions:
-    return COptions(int(precision), int(ckpt_every), int(tape_steps), int(diag_every))
+            diag_every: int = 0, lattice=D3Q19) -> COptions:
+    return COptions(int(precision), int(ckpt_every), int(tape_steps), int(diag_every),
+                    lattice_code(lattice))
 
 
 def workspace_size(members: Sequence, opt: COptions) -> int:
@@ -143,11 +156,12 @@ class Simulation:
 
     ``fields``: (n0, eps0, u0) as float64 torch tensors on the GPU (or numpy
     arrays, copied once). For a batch, pass flat per-member concatenations.
+    ``lattice``: D3Q19 (default) or D2Q9 (or their names).
     """
 
     def __init__(self, members: Sequence, n0, eps0, u0, precision: int = FP32,
                  ckpt_every: int = 0, tape_steps: int = 0, diag_every: int = 0,
-                 stream=None, device: Optional[int] = None):
+                 stream=None, device: Optional[int] = None, lattice=D3Q19):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1211_3286_amd needs a ROCm GPU; none is visible")
@@ -157,7 +171,9 @@ class Simulation:
         self.ncells = sum(int(p.nx) * int(p.ny) * int(p.nz) for p in self.members)
         dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.device = dev
-        self.opt = options(precision, ckpt_every, tape_steps, diag_every)
+        self.lattice = lattice_code(lattice)
+        self.q = 9 if self.lattice == D2Q9 else 19
+        self.opt = options(precision, ckpt_every, tape_steps, diag_every, self.lattice)
         self._arr = cparams(self.members)
         self.ws_bytes = workspace_size(self.members, self.opt)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
@@ -252,10 +268,10 @@ class Simulation:
         return np.array(s[:]), int(st.value), int(bad.value)
 
     def populations(self):
-        """(f, g) as float64 device tensors of shape (19, ncells)."""
+        """(f, g) as float64 device tensors of shape (Q, ncells), Q = 19 or 9."""
         torch = self.torch
-        f = torch.empty(19, self.ncells, dtype=torch.float64, device=self.device)
-        g = torch.empty(19, self.ncells, dtype=torch.float64, device=self.device)
+        f = torch.empty(self.q, self.ncells, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.q, self.ncells, dtype=torch.float64, device=self.device)
         _check(lib().rlb_populations(self.h, _dptr(f), _dptr(g), 1), "rlb_populations")
         return f, g
 
@@ -327,7 +343,8 @@ class Simulation:
         dev = torch.cuda.get_device_name(self.device)
         shapes = [(int(p.nx), int(p.ny), int(p.nz)) for p in self.members]
         shape = shapes[0] if len(shapes) == 1 else f"{len(shapes)}x{self.ncells}"
-        return f"{dev}|{'fp32' if self.precision == FP32 else 'fp64'}|{shape}"
+        lat = "d2q9|" if self.lattice == D2Q9 else ""
+        return f"{dev}|{lat}{'fp32' if self.precision == FP32 else 'fp64'}|{shape}"
 
 
 def problem_fields(problems) -> tuple:
@@ -344,6 +361,10 @@ def from_problems(problems, **kw) -> Simulation:
     """A Simulation of one problem or a batch of them (workloads.Problem)."""
     if not isinstance(problems, (list, tuple)):
         problems = [problems]
+    lats = {getattr(p.params, "lattice", "d3q19") for p in problems}
+    if len(lats) != 1:
+        raise ValueError("every member of a batch uses the same lattice model")
+    kw.setdefault("lattice", lats.pop())
     n, e, u = problem_fields(problems)
     return Simulation([p.params for p in problems], n, e, u, **kw)
 

@@ -16,8 +16,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librlb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "adjoint.hip", "api.cpp"]
-HEADERS = ["cell.hpp", "adjoint_cell.hpp", "device_util.hpp", "internal.hpp", "adjoint.hpp"]
+SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "api.cpp"]
+HEADERS = ["cell.hpp", "cell2d.hpp", "adjoint_cell.hpp", "device_util.hpp", "internal.hpp",
+           "adjoint.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -29,9 +29,11 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int64_t ncells = 0, cs = 0;
   size_t esz = 0;
-  size_t off_descs = 0, off_small = 0, off_partials = 0, off_buf0 = 0, off_buf1 = 0;
+  size_t off_descs = 0, off_small = 0, off_partials = 0, off_xparts = 0, off_buf0 = 0,
+         off_buf1 = 0;
   size_t off_stage = 0, off_segs = 0, off_flags = 0, off_tape = 0, total = 0;
   int max_parts = 0;
+  int export_parts = 0;  // blocks of the field export (its own partials region)
   int64_t max_segs = 0;  // persistent path: one segment per z-plane at most
   rlb::TapeLayout tape;
 };
@@ -66,12 +68,22 @@ bool lattice_path(int32_t n_members, int64_t ncells) {
   return n_members == 1 && ncells >= kLatticeMinCells;
 }
 
+// Velocities per distribution of a lattice kind.
+int nvel(int32_t lattice) { return lattice == RLB_D2Q9 ? 9 : 19; }
+
 rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, Layout& L) {
   if (!opt) return RLB_E_ARG;
   if (opt->precision != RLB_FP32 && opt->precision != RLB_FP64) return RLB_E_ARG;
   if (opt->ckpt_every < 0 || opt->tape_steps < 0 || opt->diag_every < 0) return RLB_E_ARG;
+  if (opt->lattice != RLB_D3Q19 && opt->lattice != RLB_D2Q9) return RLB_E_ARG;
   rlb_status st = check_members(m, n, &L.ncells);
   if (st != RLB_OK) return st;
+  const bool d2 = opt->lattice == RLB_D2Q9;
+  if (d2) {
+    for (int i = 0; i < n; ++i)
+      if (m[i].nz != 1) return RLB_E_ARG;
+    if (opt->ckpt_every > 0) return RLB_E_UNSUPPORTED;  // the adjoint covers D3Q19
+  }
   if (opt->ckpt_every > 0 && n != 1) return RLB_E_UNSUPPORTED;
   L.esz = opt->precision == RLB_FP32 ? 4 : 8;
   // Plane stride: a multiple of 64 elements plus 64 more, so that planes of a
@@ -86,11 +98,15 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
     g.nx = m[0].nx;
     g.ny = m[0].ny;
     g.nz = m[0].nz;
-    for (int v = 0; v < rlb::num_lattice_variants(); ++v)
-      parts = std::max(parts, rlb::lattice_partials(v, g));
+    if (d2)
+      for (int v = 0; v < rlb::d2q9_num_lattice_variants(); ++v)
+        parts = std::max(parts, rlb::d2q9_lattice_partials(v, g));
+    else
+      for (int v = 0; v < rlb::num_lattice_variants(); ++v)
+        parts = std::max(parts, rlb::lattice_partials(v, g));
   }
   parts = std::max<int64_t>(parts, (int64_t)n * rlb::kRefBlocks);
-  if (!lattice_path(n, L.ncells)) {
+  if (!lattice_path(n, L.ncells) && !d2) {  // segment tables (D3Q19 persistent path)
     for (int i = 0; i < n; ++i) L.max_segs += m[i].nz;
     parts = std::max<int64_t>(parts, L.max_segs);
   }
@@ -102,7 +118,12 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   o = align_up(o + 1024);
   L.off_partials = o;
   o = align_up(o + sizeof(double) * 5 * (size_t)L.max_parts);
-  const size_t buf = 38 * (size_t)L.cs * L.esz;
+  // The field export keeps its partial sums apart, so that rlb_moments never
+  // overwrites the diagnostics partials of the latest step.
+  L.export_parts = (int)std::min<int64_t>(std::max<int64_t>((L.ncells + 255) / 256, 1), 65536);
+  L.off_xparts = o;
+  o = align_up(o + sizeof(double) * 5 * (size_t)L.export_parts);
+  const size_t buf = 2 * (size_t)nvel(opt->lattice) * (size_t)L.cs * L.esz;
   L.off_buf0 = o;
   o = align_up(o + buf);
   L.off_buf1 = o;
@@ -157,9 +178,12 @@ struct rlb_sim {
   unsigned long long* d_count = nullptr;
   unsigned long long* d_bad_save = nullptr;
   double* d_partials = nullptr;
+  double* d_xparts = nullptr;  // export partials (rlb_moments)
   void* buf[2] = {nullptr, nullptr};
   double* d_stage = nullptr;
   int cur = 0;
+  bool d2 = false;  // D2Q9 model (9 velocities, 18 planes per buffer)
+  int q = 19;
   bool lattice = false;
   LatticeGeom geom{};
   int variant = 0;
@@ -202,19 +226,28 @@ void* state_buf(rlb_sim* h) { return h->buf[h->cur]; }
 void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
+  if (h->d2)
+    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
+                                                 h->d_partials, h->d_bad, h->stream));
   return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
                                           h->d_partials, h->d_bad, h->stream));
+}
+
+int lattice_parts(const rlb_sim* h, int variant) {
+  return h->d2 ? rlb::d2q9_lattice_partials(variant, h->geom)
+               : rlb::lattice_partials(variant, h->geom);
 }
 
 constexpr int kSpinLimit = 1 << 24;  // about a second of polling per wait
 
 bool is_segment_variant(const rlb_sim* h, int v) {
-  return !h->lattice && v >= rlb::num_member_variants() &&
+  return !h->lattice && !h->d2 && v >= rlb::num_member_variants() &&
          v < rlb::num_member_variants() + rlb::num_segment_variants();
 }
 
 bool is_tube_variant(const rlb_sim* h, int v) {
-  return !h->lattice && v >= rlb::num_member_variants() + rlb::num_segment_variants();
+  return !h->lattice && !h->d2 &&
+         v >= rlb::num_member_variants() + rlb::num_segment_variants();
 }
 
 int tube_index(int v) { return v - rlb::num_member_variants() - rlb::num_segment_variants(); }
@@ -412,7 +445,10 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
     m.step0 = step0;
     m.partials = h->d_partials;
     m.bad = h->d_bad;
-    RLB_HIP(rlb::member_kernel(h->precision, variant, &func, &block));
+    if (h->d2)
+      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, &func, &block));
+    else
+      RLB_HIP(rlb::member_kernel(h->precision, variant, &func, &block));
     args[0] = &h->margs;
     grid = dim3(h->n_members, 1, 1);
   }
@@ -455,7 +491,7 @@ rlb_status advance(rlb_sim* h, int32_t n) {
       if (st != RLB_OK) return st;
       if (diag) {
         h->diag_step = s;
-        h->diag_parts = rlb::lattice_partials(h->variant, h->geom);
+        h->diag_parts = lattice_parts(h, h->variant);
       }
       h->cur = 1 - h->cur;
       h->steps = s;
@@ -497,11 +533,12 @@ rlb_status copy_fields_in(rlb_sim* h, const double* n0, const double* eps0, cons
   return RLB_OK;
 }
 
-bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int64_t nc) {
+bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int64_t nc,
+                    bool planar) {
   for (int64_t i = 0; i < nc; ++i) {
     const double uu = u0[i] * u0[i] + u0[nc + i] * u0[nc + i] + u0[2 * nc + i] * u0[2 * nc + i];
     if (!(eps0[i] > 0.0) || !(n0[i] >= 0.0) || !(uu < 1.0) || !std::isfinite(n0[i]) ||
-        !std::isfinite(eps0[i]))
+        !std::isfinite(eps0[i]) || (planar && u0[2 * nc + i] != 0.0))
       return false;
   }
   return true;
@@ -512,6 +549,9 @@ bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int6
 namespace {
 
 const char* kernel_name_of(const rlb_sim* h, int v) {
+  if (h->d2)
+    return h->lattice ? rlb::d2q9_lattice_kernel_name(h->precision, v)
+                      : rlb::d2q9_member_kernel_name(h->precision, v);
   if (h->lattice) return rlb::lattice_kernel_name(h->precision, v);
   if (v < rlb::num_member_variants()) return rlb::member_kernel_name(h->precision, v);
   if (is_segment_variant(h, v))
@@ -570,7 +610,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   if (fields_on_device != 0 && fields_on_device != 1) return RLB_E_ARG;
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
     return RLB_E_WORKSPACE;
-  if (!fields_on_device && !host_fields_ok(n0, eps0, u0, L.ncells)) return RLB_E_UNPHYSICAL;
+  const bool planar = opt->lattice == RLB_D2Q9;
+  if (!fields_on_device && !host_fields_ok(n0, eps0, u0, L.ncells, planar))
+    return RLB_E_UNPHYSICAL;
 
   rlb_sim* h = new (std::nothrow) rlb_sim();
   if (!h) return RLB_E_ARG;
@@ -591,15 +633,18 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->d_count = h->d_bad + 1;
   h->d_bad_save = h->d_bad + 2;
   h->d_partials = (double*)(h->ws + L.off_partials);
+  h->d_xparts = (double*)(h->ws + L.off_xparts);
   h->buf[0] = h->ws + L.off_buf0;
   h->buf[1] = h->ws + L.off_buf1;
   h->d_stage = (double*)(h->ws + L.off_stage);
   h->d_segs = (rlb::Segment*)(h->ws + L.off_segs);
   h->d_flags = (unsigned long long*)(h->ws + L.off_flags);
   h->d_error = (int*)(h->d_small + 24);
+  h->d2 = planar;
+  h->q = nvel(opt->lattice);
   h->lattice = lattice_path(n_members, L.ncells);
-  h->variant = h->lattice ? 3 : 2;
-  h->all_tubes = true;
+  h->variant = h->d2 ? 2 : (h->lattice ? 3 : 2);
+  h->all_tubes = !h->d2;
   for (int i = 0; i < n_members; ++i)
     if (members[i].nx != 1 || members[i].ny != 1) h->all_tubes = false;
 
@@ -642,7 +687,8 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   if (copy_fields_in(h, n0, eps0, u0, fields_on_device, &dn, &de, &du) != RLB_OK)
     return fail(RLB_E_DEVICE);
   if (fields_on_device) {
-    if (rlb::launch_validate(dn, de, du, L.ncells, h->d_count, h->stream) != hipSuccess)
+    if (rlb::launch_validate(dn, de, du, L.ncells, planar ? 1 : 0, h->d_count, h->stream) !=
+        hipSuccess)
       return fail(RLB_E_DEVICE);
     unsigned long long cnt = 0;
     if (hipMemcpyAsync(&cnt, h->d_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream) !=
@@ -657,9 +703,12 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   if (rlb::launch_member_refs(h->d_descs, n_members, dn, de, du, L.ncells, h->d_partials,
                               h->stream) != hipSuccess)
     return fail(RLB_E_DEVICE);
-  if (rlb::launch_init(h->precision, h->buf[0], L.cs, h->d_descs, n_members, dn, de, du,
-                       L.ncells, h->stream) != hipSuccess)
-    return fail(RLB_E_DEVICE);
+  const hipError_t ie =
+      planar ? rlb::d2q9_launch_init(h->precision, h->buf[0], L.cs, h->d_descs, n_members, dn,
+                                     de, du, L.ncells, h->stream)
+             : rlb::launch_init(h->precision, h->buf[0], L.cs, h->d_descs, n_members, dn, de, du,
+                                L.ncells, h->stream);
+  if (ie != hipSuccess) return fail(RLB_E_DEVICE);
   if (hipMemcpyAsync(h->descs.data(), h->d_descs, sizeof(MemberDesc) * n_members,
                      hipMemcpyDeviceToHost, h->stream) != hipSuccess ||
       hipStreamSynchronize(h->stream) != hipSuccess)
@@ -731,11 +780,15 @@ rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* 
     dg = gamma ? s + 3 * nc : nullptr;
     du = u ? s + 4 * nc : nullptr;
   }
-  int nparts = (int)std::min<int64_t>(std::max<int64_t>((nc + 255) / 256, 1), 65536);
-  nparts = std::min(nparts, h->L.max_parts);
-  RLB_HIP(rlb::launch_export(h->precision, state_buf(h), h->L.cs, h->d_descs, h->n_members, nc,
-                             dn, de, dP, dg, du, h->d_partials, nparts, h->stream));
-  RLB_HIP(rlb::launch_reduce(h->d_partials, nparts, h->d_small, h->stream));
+  const int nparts = h->L.export_parts;
+  if (h->d2)
+    RLB_HIP(rlb::d2q9_launch_export(h->precision, state_buf(h), h->L.cs, h->d_descs,
+                                    h->n_members, nc, dn, de, dP, dg, du, h->d_xparts, nparts,
+                                    h->stream));
+  else
+    RLB_HIP(rlb::launch_export(h->precision, state_buf(h), h->L.cs, h->d_descs, h->n_members,
+                               nc, dn, de, dP, dg, du, h->d_xparts, nparts, h->stream));
+  RLB_HIP(rlb::launch_reduce(h->d_xparts, nparts, h->d_small, h->stream));
   double hs[5];
   unsigned long long bad = 0;
   RLB_HIP(hipMemcpyAsync(hs, h->d_small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
@@ -780,24 +833,27 @@ rlb_status rlb_populations(rlb_handle h, double* f, double* g, int32_t out_on_de
   DeviceGuard dg(h->device);
   if (!dg.ok) return RLB_E_DEVICE;
   const int64_t nc = h->L.ncells;
+  const int Q = h->q;
+  auto planes = [&](int p0, int np, double* out) {
+    return h->d2 ? rlb::d2q9_launch_population_planes(h->precision, state_buf(h), h->L.cs,
+                                                      h->d_descs, h->n_members, nc, p0, np, out,
+                                                      h->stream)
+                 : rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs,
+                                                 h->d_descs, h->n_members, nc, p0, np, out,
+                                                 h->stream);
+  };
   if (out_on_device) {
-    if (f)
-      RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
-                                            h->n_members, nc, 0, 19, f, h->stream));
-    if (g)
-      RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
-                                            h->n_members, nc, 19, 19, g, h->stream));
+    if (f) RLB_HIP(planes(0, Q, f));
+    if (g) RLB_HIP(planes(Q, Q, g));
   } else {
     // staging holds 8 planes: convert f (then g) in chunks of up to 8 planes
     double* s = h->d_stage;
     for (int which = 0; which < 2; ++which) {
       double* hostp = which ? g : f;
       if (!hostp) continue;
-      for (int a0 = 0; a0 < 19; a0 += 8) {
-        const int na = std::min(8, 19 - a0);
-        RLB_HIP(rlb::launch_population_planes(h->precision, state_buf(h), h->L.cs, h->d_descs,
-                                              h->n_members, nc, which * 19 + a0, na, s,
-                                              h->stream));
+      for (int a0 = 0; a0 < Q; a0 += 8) {
+        const int na = std::min(8, Q - a0);
+        RLB_HIP(planes(which * Q + a0, na, s));
         RLB_HIP(hipMemcpyAsync(hostp + (size_t)a0 * nc, s, sizeof(double) * na * nc,
                                hipMemcpyDeviceToHost, h->stream));
         RLB_HIP(hipStreamSynchronize(h->stream));
@@ -831,9 +887,12 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
 
 rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
   if (!h || !count) return RLB_E_ARG;
-  *count = h->lattice ? rlb::num_lattice_variants()
-                      : rlb::num_member_variants() + rlb::num_segment_variants() +
-                            rlb::num_tube_variants();
+  if (h->d2)
+    *count = h->lattice ? rlb::d2q9_num_lattice_variants() : rlb::d2q9_num_member_variants();
+  else
+    *count = h->lattice ? rlb::num_lattice_variants()
+                        : rlb::num_member_variants() + rlb::num_segment_variants() +
+                              rlb::num_tube_variants();
   return RLB_OK;
 }
 

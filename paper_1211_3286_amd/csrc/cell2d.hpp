@@ -1,0 +1,274 @@
+// Per-cell arithmetic of the D2Q9 MRT model of Sec. V.A (device).
+//
+// The model the paper itself runs for its MRT study: Eqs. (30)-(35) on the
+// D2Q9 lattice of an nx x ny x 1 lattice (x and y are the lattice axes).
+// Velocities (order of rlb.h for RLB_D2Q9):
+//   0 (0,0)  1 (1,0)  2 (0,1)  3 (-1,0)  4 (0,-1)
+//   5 (1,1)  6 (-1,1)  7 (-1,-1)  8 (1,-1)
+// opposite pairs (1,3), (2,4), (5,7), (6,8); weights 4/9, 1/9, 1/36.
+//
+// Storage, as for D3Q19: deviations from the member's rest reference state,
+//   f_a = w_a n_r + f~_a,   g_a = gref_a + g~_a,
+//   gref = (4/3 P_r, P_r/3 on the axes, P_r/12 on the diagonals)
+//        = g_eq of Eqs. (32)-(33) at sigma = 4 P_r, P = P_r, u = 0.
+//
+// Moment basis (rows rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy; squared
+// norms 9, 36, 36, 6, 12, 6, 12, 4, 4): the orthogonal D2Q9 basis that turns
+// g_eq into the m_eq printed as Eq. (34):
+//   e = -4 sigma + 3 sigma u^2 + 10 P,   eps = 4 sigma - 3 sigma u^2 - 13 P,
+//   q = -sigma u,   p_xx = sigma (u_x^2 - u_y^2),   p_xy = sigma u_x u_y,
+// and rho = sigma - P, j = sigma u (conserved: tau_sigma = tau_j = dt).
+// S of Eq. (31): e <- 1/tau_e, eps <- 1/tau_eps, q <- 1/tau_q, p <- 1/tau_v.
+// M has small integer entries, so m = M g and g* = g - M^T diag(1/|row|^2)
+// S (m - m_eq) are written out on sums and differences of opposite pairs.
+// The recovery is the D3Q19 one (Eq. 10 with P = eps/3) with M_z = 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cell.hpp"
+#include "device_util.hpp"
+
+namespace rlb {
+namespace d2q9 {
+
+__host__ __device__ constexpr int ex(int a) {
+  constexpr int t[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  return t[a];
+}
+__host__ __device__ constexpr int ey(int a) {
+  constexpr int t[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  return t[a];
+}
+__host__ __device__ constexpr double weight(int a) {
+  return a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+// Reference g populations in units of P_r.
+__host__ __device__ constexpr double gref_unit(int a) {
+  return a == 0 ? 4.0 / 3.0 : (a < 5 ? 1.0 / 3.0 : 1.0 / 12.0);
+}
+
+constexpr double kNormE = 36.0, kNormEps = 36.0, kNormQ = 12.0, kNormP = 4.0;
+
+// FP64 Eq. (10) sums from the stored deviations: N = n_r + fs, E = 3 P_r + gs,
+// M = sum e g~ (the reference carries no momentum).
+template <typename C>
+__device__ __forceinline__ void cell_sums(const C (&f)[9], const C (&g)[9], const Ref& ref,
+                                          double& N, double& E, double& Mx, double& My,
+                                          double& fs, double& gs) {
+  double gd[9];
+  fs = 0.0;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    fs += (double)f[a];
+    gd[a] = (double)g[a];
+  }
+  const double D1 = gd[1] - gd[3], D2 = gd[2] - gd[4], D5 = gd[5] - gd[7], D6 = gd[6] - gd[8];
+  gs = gd[0] + ((gd[1] + gd[3]) + (gd[2] + gd[4])) + ((gd[5] + gd[7]) + (gd[6] + gd[8]));
+  N = ref.n + fs;
+  E = 3.0 * ref.P + gs;
+  Mx = D1 + (D5 - D6);
+  My = D2 + (D5 + D6);
+}
+
+// The six non-conserved moments.
+template <typename C>
+struct NonConserved {
+  C e, eps, qx, qy, pxx, pxy;
+};
+
+template <typename C>
+__device__ __forceinline__ NonConserved<C> moments_nc(const C (&g)[9]) {
+  const C S1 = g[1] + g[3], S2 = g[2] + g[4], S5 = g[5] + g[7], S6 = g[6] + g[8];
+  const C D1 = g[1] - g[3], D2 = g[2] - g[4], D5 = g[5] - g[7], D6 = g[6] - g[8];
+  const C Sa = S1 + S2, Sd = S5 + S6;
+  NonConserved<C> m;
+  m.e = C(-4.0) * g[0] - Sa + C(2.0) * Sd;
+  m.eps = C(4.0) * g[0] - C(2.0) * Sa + Sd;
+  m.qx = C(-2.0) * D1 + D5 - D6;
+  m.qy = C(-2.0) * D2 + D5 + D6;
+  m.pxx = S1 - S2;
+  m.pxy = S5 - S6;
+  return m;
+}
+
+// Eq. (34) on the non-conserved rows minus the reference's moments
+// (e of gref = -6 P_r, eps of gref = 3 P_r).
+template <typename C>
+__device__ __forceinline__ NonConserved<C> equilibrium_nc(const Macro& mac, const Ref& ref) {
+  const double sd = mac.sigma, Pd = mac.P, u2d = mac.u2;
+  const C sg = (C)sd, ux = (C)mac.ux, uy = (C)mac.uy;
+  NonConserved<C> q;
+  q.e = (C)(-4.0 * sd + 3.0 * sd * u2d + 10.0 * Pd + 6.0 * ref.P);
+  q.eps = (C)(4.0 * sd - 3.0 * sd * u2d - 13.0 * Pd - 3.0 * ref.P);
+  q.qx = -(sg * ux);
+  q.qy = -(sg * uy);
+  q.pxx = sg * (ux * ux - uy * uy);
+  q.pxy = sg * ux * uy;
+  return q;
+}
+
+// c_k = s_k (m_k - m_eq,k) / |row_k|^2.
+template <typename C>
+__device__ __forceinline__ NonConserved<C> scaled_deviation(const NonConserved<C>& m,
+                                                            const NonConserved<C>& q,
+                                                            const Rates& rt) {
+  const C se = (C)rt.s_e, seps = (C)rt.s_eps, sq = (C)rt.s_q, sv = (C)rt.s_v;
+  NonConserved<C> c;
+  c.e = se * (m.e - q.e) * C(1.0 / kNormE);
+  c.eps = seps * (m.eps - q.eps) * C(1.0 / kNormEps);
+  c.qx = sq * (m.qx - q.qx) * C(1.0 / kNormQ);
+  c.qy = sq * (m.qy - q.qy) * C(1.0 / kNormQ);
+  c.pxx = sv * (m.pxx - q.pxx) * C(1.0 / kNormP);
+  c.pxy = sv * (m.pxy - q.pxy) * C(1.0 / kNormP);
+  return c;
+}
+
+// g <- g - M^T c (non-conserved rows only).
+template <typename C>
+__device__ __forceinline__ void sub_MT(C (&g)[9], const NonConserved<C>& c) {
+  const C axis = -c.e - C(2.0) * c.eps;
+  const C diag = C(2.0) * c.e + c.eps;
+  const C ax_x = axis + c.pxx, ax_y = axis - c.pxx;
+  const C qx2 = C(2.0) * c.qx, qy2 = C(2.0) * c.qy;
+  const C dp = diag + c.pxy, dm = diag - c.pxy;
+  const C sp = c.qx + c.qy, sm = c.qx - c.qy;
+  g[0] = g[0] - (C(-4.0) * c.e + C(4.0) * c.eps);
+  g[1] = g[1] - (ax_x - qx2);
+  g[3] = g[3] - (ax_x + qx2);
+  g[2] = g[2] - (ax_y - qy2);
+  g[4] = g[4] - (ax_y + qy2);
+  g[5] = g[5] - (dp + sp);
+  g[7] = g[7] - (dp - sp);
+  g[6] = g[6] - (dm - sm);
+  g[8] = g[8] - (dm + sm);
+}
+
+// f: BGK of Eq. (5) with f_eq of Eq. (7)'s form and the D2Q9 weights.
+template <typename C>
+__device__ __forceinline__ void collide_f(C (&f)[9], double N, double fs, const Macro& mac,
+                                          const Rates& rt, const Ref& ref) {
+  const C ux = (C)mac.ux, uy = (C)mac.uy, uu = (C)mac.u2;
+  const C Nc = (C)N;
+  const C b = (C)(N - ref.n) - C(1.5) * Nc * uu;
+  const C a3 = C(3.0) * Nc, a45 = C(4.5) * Nc;
+  const C wf = (C)rt.w_f;
+  C eu[9];
+  eu[0] = C(0.0);
+  eu[1] = ux;
+  eu[2] = uy;
+  eu[3] = -ux;
+  eu[4] = -uy;
+  eu[5] = ux + uy;
+  eu[6] = uy - ux;
+  eu[7] = -(ux + uy);
+  eu[8] = ux - uy;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const C w = a == 0 ? C(4.0 / 9.0) : (a < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+    const C feq = w * (b + a3 * eu[a] + a45 * eu[a] * eu[a]);
+    f[a] = f[a] + wf * (feq - f[a]);
+  }
+  // FP32 storage: the rest population takes back the rounding residual of
+  // the particle number, computed in FP64 (as for D3Q19).
+  if constexpr (sizeof(C) == 4) {
+    double fo = 0.0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) fo += (double)f[a];
+    f[0] = (C)(fs - fo);
+  }
+}
+
+// g: MRT of Eq. (35) in place.
+template <typename C>
+__device__ __forceinline__ void collide_g(C (&g)[9], double Mx, double My, double gs,
+                                          const Macro& mac, const Rates& rt, const Ref& ref) {
+  d2q9::sub_MT(g, d2q9::scaled_deviation(d2q9::moments_nc(g),
+                                         d2q9::equilibrium_nc<C>(mac, ref), rt));
+  // FP32 storage: momentum residual into g_1 (x) and g_2 (y), then the
+  // energy residual into the rest population, in FP64.
+  if constexpr (sizeof(C) == 4) {
+    double gd[9];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) gd[a] = (double)g[a];
+    const double mx = (gd[1] - gd[3]) + ((gd[5] - gd[7]) - (gd[6] - gd[8]));
+    const double my = (gd[2] - gd[4]) + ((gd[5] - gd[7]) + (gd[6] - gd[8]));
+    g[1] = (C)(gd[1] + (Mx - mx));
+    g[2] = (C)(gd[2] + (My - my));
+    gd[1] = (double)g[1];
+    gd[2] = (double)g[2];
+    double go = 0.0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) go += gd[a];
+    g[0] = (C)(gs - go);
+  }
+}
+
+// One collision of both distributions; false (cell untouched) if inadmissible.
+template <typename C>
+__device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt, const Ref& ref,
+                                        Sums& sums) {
+  double N, E, Mx, My, fs, gs;
+  d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
+  sums.v[0] = N;
+  sums.v[1] = E;
+  sums.v[2] = Mx;
+  sums.v[3] = My;
+  sums.v[4] = 0.0;
+  Macro mac;
+  if (!recover(E, Mx, My, 0.0, mac)) return false;
+  d2q9::collide_f(f, N, fs, mac, rt, ref);
+  d2q9::collide_g(g, Mx, My, gs, mac, rt, ref);
+  return true;
+}
+
+// Equilibrium deviations of a cell from its fields (Eqs. 7, 32, 33), FP64.
+__device__ __forceinline__ void equilibrium_dev(double n, double eps, double ux, double uy,
+                                                const Ref& ref, double (&f)[9],
+                                                double (&g)[9]) {
+  const double uu = ux * ux + uy * uy;
+  const double gam2 = 1.0 / (1.0 - uu);
+  const double N = n * sqrt(gam2);
+  const double P = eps / 3.0;
+  const double sigma = (eps + P) * gam2;
+#pragma unroll
+  for (int a = 0; a < 9; ++a) {
+    const double eu = ex(a) * ux + ey(a) * uy;
+    const double w = weight(a);
+    f[a] = w * (N * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - ref.n);
+    double gv;
+    if (a == 0)
+      gv = w * (2.25 * sigma - 6.0 * P - 1.5 * sigma * uu);
+    else
+      gv = w * (3.0 * P + 3.0 * sigma * eu + 4.5 * sigma * eu * eu - 1.5 * sigma * uu);
+    g[a] = gv - gref_unit(a) * ref.P;
+  }
+}
+
+// Byte offsets of the 9 pull sources of cell (x, y) (source = cell - e_a,
+// clamped or wrapped per axis).
+__device__ __forceinline__ void pull_offsets(int x, int y, int nx, int ny, int bcx, int bcy,
+                                             uint32_t base, uint32_t esz, uint32_t (&off)[9],
+                                             uint32_t& self) {
+  const int xm = nbr(x, -1, nx, bcx), xp = nbr(x, 1, nx, bcx);
+  const int ym = nbr(y, -1, ny, bcy), yp = nbr(y, 1, ny, bcy);
+  const uint32_t unx = (uint32_t)nx;
+  const uint32_t r_c = base + (uint32_t)y * unx;
+  const uint32_t r_ym = base + (uint32_t)ym * unx;
+  const uint32_t r_yp = base + (uint32_t)yp * unx;
+  const uint32_t X = (uint32_t)x, XM = (uint32_t)xm, XP = (uint32_t)xp;
+  off[0] = (r_c + X) * esz;
+  off[1] = (r_c + XM) * esz;
+  off[2] = (r_ym + X) * esz;
+  off[3] = (r_c + XP) * esz;
+  off[4] = (r_yp + X) * esz;
+  off[5] = (r_ym + XM) * esz;
+  off[6] = (r_ym + XP) * esz;
+  off[7] = (r_yp + XP) * esz;
+  off[8] = (r_yp + XM) * esz;
+  self = off[0];
+}
+
+}  // namespace d2q9
+}  // namespace rlb

@@ -48,8 +48,9 @@ constexpr int kRefBlocks = 64;
 hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const double* n0,
                               const double* eps0, const double* u0, int64_t ncells,
                               double* parts, hipStream_t s);
+// planar: also count cells with u_z != 0 (D2Q9 lattices carry no z velocity).
 hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
-                           int64_t ncells, unsigned long long* count, hipStream_t s);
+                           int64_t ncells, int planar, unsigned long long* count, hipStream_t s);
 hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
                        int n_members, const double* n0, const double* eps0, const double* u0,
                        int64_t ncells, hipStream_t s);
@@ -149,5 +150,27 @@ hipError_t launch_population_planes(int precision, const void* state, int64_t cs
 hipError_t launch_reduce(const double* partials, int nparts, double* out5, hipStream_t s);
 const char* lattice_kernel_name(int precision, int variant);
 const char* member_kernel_name(int precision, int variant);
+
+// D2Q9 model (kernels2d.hip): 18 planes per buffer, nz = 1. LatticeVariant
+// cz is the number of cells per thread along y.
+int d2q9_num_lattice_variants();
+int d2q9_lattice_partials(int variant, const LatticeGeom& g);
+const char* d2q9_lattice_kernel_name(int precision, int variant);
+hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, const void* src,
+                                    void* dst, const LatticeGeom& g, double* partials,
+                                    unsigned long long* bad, hipStream_t s);
+int d2q9_num_member_variants();
+hipError_t d2q9_member_kernel(int precision, int variant, const void** func, dim3* block);
+const char* d2q9_member_kernel_name(int precision, int variant);
+hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
+                            int n_members, const double* n0, const double* eps0,
+                            const double* u0, int64_t ncells, hipStream_t s);
+hipError_t d2q9_launch_export(int precision, const void* state, int64_t cs,
+                              const MemberDesc* descs, int n_members, int64_t ncells, double* n,
+                              double* eps, double* P, double* gamma, double* u,
+                              double* partials, int nparts, hipStream_t s);
+hipError_t d2q9_launch_population_planes(int precision, const void* state, int64_t cs,
+                                         const MemberDesc* descs, int n_members, int64_t ncells,
+                                         int p0, int np, double* out, hipStream_t s);
 
 }  // namespace rlb

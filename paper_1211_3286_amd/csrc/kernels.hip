@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64) void k_member_ref_final(MemberDesc* descs, cons
 }
 
 __global__ __launch_bounds__(256) void k_validate(const double* n0, const double* eps0,
-                                                  const double* u0, int64_t ncells,
+                                                  const double* u0, int64_t ncells, int planar,
                                                   unsigned long long* count) {
   int nb = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void k_validate(const double* n0, const double
     const double ux = u0[i], uy = u0[ncells + i], uz = u0[2 * ncells + i];
     const double uu = ux * ux + uy * uy + uz * uz;
     const bool ok = (eps0[i] > 0.0) && (n0[i] >= 0.0) && (uu < 1.0) && (n0[i] < INFINITY) &&
-                    (eps0[i] < INFINITY);
+                    (eps0[i] < INFINITY) && (!planar || uz == 0.0);
     nb += ok ? 0 : 1;
   }
   if (nb) atomicAdd(count, (unsigned long long)nb);
@@ -643,9 +643,9 @@ hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const doub
 }
 
 hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
-                           int64_t ncells, unsigned long long* count, hipStream_t s) {
+                           int64_t ncells, int planar, unsigned long long* count, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(ncells)), dim3(256), 0, s, n0, eps0, u0, ncells,
-                     count);
+                     planar, count);
   return hipGetLastError();
 }
 

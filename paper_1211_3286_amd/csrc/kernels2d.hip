@@ -1,0 +1,361 @@
+// Kernels of the D2Q9 MRT model (Sec. V.A) for gfx950.
+//
+// Population storage (one buffer): 18 planes of cs elements, planes 0..8 hold
+// f_a and planes 9..17 hold g_a (D2Q9 velocity order of rlb.h). Two buffers
+// alternate (A/B), as for D3Q19. The fused step reads 18 values per cell,
+// collides in registers (cell2d.hpp) and writes 18: 2 x 18 x sizeof(T) bytes
+// of HBM traffic per cell update.
+
+#include <hip/hip_runtime.h>
+
+#include "cell2d.hpp"
+#include "device_util.hpp"
+#include "internal.hpp"
+
+namespace rlb {
+
+namespace {
+
+// -------------------------------------------------------------------------
+// Fused step on one nx x ny lattice: grid (ceil(nx/BX), ceil(ny/(BY*CY))),
+// block (BX, BY); each thread updates CY cells along y.
+// -------------------------------------------------------------------------
+template <typename T, int BX, int BY, int CY, bool DIAG>
+__global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ src,
+                                                        T* __restrict__ dst, LatticeGeom geo,
+                                                        double* __restrict__ partials,
+                                                        unsigned long long* __restrict__ bad) {
+  const int x = blockIdx.x * BX + threadIdx.x;
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int nbad = 0;
+  const uint32_t esz = sizeof(T);
+#pragma unroll 1
+  for (int k = 0; k < CY; ++k) {
+    const int y = (blockIdx.y * CY + k) * BY + threadIdx.y;
+    if (x < geo.nx && y < geo.ny) {
+      uint32_t off[9], self;
+      d2q9::pull_offsets(x, y, geo.nx, geo.ny, geo.bcx, geo.bcy, 0u, esz, off, self);
+      T f[9], g[9];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
+        g[a] = ld(src + (int64_t)(9 + a) * geo.cs, off[a]);
+      }
+      Sums s;
+      const bool ok = d2q9::collide<T>(f, g, geo.rt, geo.ref, s);
+      nbad += ok ? 0 : 1;
+      if (DIAG)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+      for (int a = 0; a < 9; ++a) {
+        st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+        st_nt(dst + (int64_t)(9 + a) * geo.cs, self, g[a]);
+      }
+    }
+  }
+  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (DIAG) {
+    block_sum5<BX * BY>(acc, tid);
+    if (tid == 0) {
+      const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) partials[b * 5 + i] = acc[i];
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
+// Persistent step over a batch of D2Q9 members: one block per member, all
+// nsteps in the launch with a block barrier between steps.
+// -------------------------------------------------------------------------
+template <typename T, int NT, int CPT>
+__global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
+  const MemberDesc d = a.descs[blockIdx.x];
+  const int tid = threadIdx.x;
+  const uint32_t esz = sizeof(T);
+  const uint32_t base = (uint32_t)d.offset;
+  int nbad = 0;
+  for (int t = 0; t < a.nsteps; ++t) {
+    const bool odd = a.pingpong && (t & 1);
+    const T* __restrict__ src = (const T*)(odd ? a.bufB : a.bufA);
+    T* __restrict__ dst = (T*)(odd ? a.bufA : a.bufB);
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag = a.diag_every > 0 && ((sidx % a.diag_every) == 0 || t == a.nsteps - 1);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < d.ncells; c0 += NT * CPT) {
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        const int c = c0 + k * NT + tid;
+        if (c < d.ncells) {
+          const int y = c / d.nx;
+          const int x = c - y * d.nx;
+          uint32_t off[9], self;
+          d2q9::pull_offsets(x, y, d.nx, d.ny, d.bcx, d.bcy, base, esz, off, self);
+          T f[9], g[9];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            f[q] = ld(src + (int64_t)q * a.cs, off[q]);
+            g[q] = ld(src + (int64_t)(9 + q) * a.cs, off[q]);
+          }
+          Sums s;
+          const bool ok = d2q9::collide<T>(f, g, d.rt, d.ref, s);
+          nbad += ok ? 0 : 1;
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            st(dst + (int64_t)q * a.cs, self, f[q]);
+            st(dst + (int64_t)(9 + q) * a.cs, self, g[q]);
+          }
+        }
+      }
+    }
+    if (diag) {
+      block_sum5<NT>(acc, tid);
+      if (tid == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
+    }
+    __syncthreads();
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
+__device__ __forceinline__ int member_of(const MemberDesc* __restrict__ d, int n, int64_t c) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].offset <= c)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_d2q9_init(T* state, int64_t cs, const MemberDesc* descs,
+                                                   int n_members, const double* n0,
+                                                   const double* eps0, const double* u0,
+                                                   int64_t ncells) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[member_of(descs, n_members, i)].ref;
+    double f[9], g[9];
+    d2q9::equilibrium_dev(n0[i], eps0[i], u0[i], u0[ncells + i], ref, f, g);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      state[a * cs + i] = (T)f[a];
+      state[(9 + a) * cs + i] = (T)g[a];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_d2q9_export(const T* state, int64_t cs,
+                                                     const MemberDesc* descs, int n_members,
+                                                     int64_t ncells, double* n, double* eps,
+                                                     double* P, double* gamma, double* u,
+                                                     double* partials) {
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[member_of(descs, n_members, i)].ref;
+    T f[9], g[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      f[a] = state[a * cs + i];
+      g[a] = state[(9 + a) * cs + i];
+    }
+    double N, E, Mx, My, fs, gs;
+    d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
+    acc[0] += N;
+    acc[1] += E;
+    acc[2] += Mx;
+    acc[3] += My;
+    Macro m;
+    const bool ok = recover(E, Mx, My, 0.0, m);
+    const double nan = __builtin_nan("");
+    const double e = ok ? 0.75 * m.sigma * (1.0 - m.u2) : nan;
+    const double gm = ok ? 1.0 / sqrt(1.0 - m.u2) : nan;
+    if (n) n[i] = ok ? N / gm : nan;
+    if (eps) eps[i] = e;
+    if (P) P[i] = ok ? e / 3.0 : nan;
+    if (gamma) gamma[i] = gm;
+    if (u) {
+      u[i] = ok ? m.ux : nan;
+      u[ncells + i] = ok ? m.uy : nan;
+      u[2 * ncells + i] = ok ? 0.0 : nan;
+    }
+  }
+  block_sum5<256>(acc, threadIdx.x);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) partials[(int64_t)blockIdx.x * 5 + k] = acc[k];
+}
+
+// Planes [p0, p0 + np) as FP64 populations (reference added back); plane
+// p < 9 is f_p, p >= 9 is g_(p-9). out[(p - p0) * ncells + cell].
+template <typename T>
+__global__ __launch_bounds__(256) void k_d2q9_planes(const T* state, int64_t cs,
+                                                     const MemberDesc* descs, int n_members,
+                                                     int64_t ncells, int p0, int np,
+                                                     double* out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
+       i += (int64_t)gridDim.x * 256) {
+    const Ref ref = descs[member_of(descs, n_members, i)].ref;
+    for (int p = p0; p < p0 + np; ++p) {
+      const double r = p < 9 ? d2q9::weight(p) * ref.n : d2q9::gref_unit(p - 9) * ref.P;
+      out[(int64_t)(p - p0) * ncells + i] = (double)state[p * cs + i] + r;
+    }
+  }
+}
+
+// ------------------------------ variants ---------------------------------
+constexpr LatticeVariant kLat2[] = {{64, 1, 1},  {128, 1, 1}, {256, 1, 1}, {64, 4, 1},
+                                    {128, 2, 1}, {256, 1, 2}, {256, 1, 4}, {128, 2, 4}};
+constexpr int kNumLat2 = sizeof(kLat2) / sizeof(kLat2[0]);
+constexpr MemberVariant kMem2[] = {{256, 1}, {512, 1}, {1024, 1}, {512, 2}, {1024, 2}};
+constexpr int kNumMem2 = sizeof(kMem2) / sizeof(kMem2[0]);
+
+int grid2_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T, int BX, int BY, int CY>
+hipError_t lat2_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
+                       double* partials, unsigned long long* bad, hipStream_t s) {
+  dim3 block(BX, BY, 1);
+  dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY * CY - 1) / (BY * CY), 1);
+  if (diag)
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true>), grid, block, 0, s, (const T*)src,
+                       (T*)dst, g, partials, bad);
+  else
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t lat2_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
+                         double* partials, unsigned long long* bad, hipStream_t s) {
+  switch (v) {
+    case 0: return lat2_launch<T, 64, 1, 1>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat2_launch<T, 128, 1, 1>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat2_launch<T, 256, 1, 1>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat2_launch<T, 64, 4, 1>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat2_launch<T, 128, 2, 1>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat2_launch<T, 256, 1, 2>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat2_launch<T, 256, 1, 4>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat2_launch<T, 128, 2, 4>(diag, src, dst, g, partials, bad, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+const void* mem2_func(int v) {
+  switch (v) {
+    case 0: return (const void*)&k_d2q9_members<T, 256, 1>;
+    case 1: return (const void*)&k_d2q9_members<T, 512, 1>;
+    case 2: return (const void*)&k_d2q9_members<T, 1024, 1>;
+    case 3: return (const void*)&k_d2q9_members<T, 512, 2>;
+    case 4: return (const void*)&k_d2q9_members<T, 1024, 2>;
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+int d2q9_num_lattice_variants() { return kNumLat2; }
+
+int d2q9_lattice_partials(int v, const LatticeGeom& g) {
+  const LatticeVariant lv = kLat2[v];
+  return ((g.nx + lv.bx - 1) / lv.bx) * ((g.ny + lv.by * lv.cz - 1) / (lv.by * lv.cz));
+}
+
+const char* d2q9_lattice_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_d2q9_lattice<float,64,1,1>",  "k_d2q9_lattice<float,128,1,1>",
+                              "k_d2q9_lattice<float,256,1,1>", "k_d2q9_lattice<float,64,4,1>",
+                              "k_d2q9_lattice<float,128,2,1>", "k_d2q9_lattice<float,256,1,2>",
+                              "k_d2q9_lattice<float,256,1,4>", "k_d2q9_lattice<float,128,2,4>"};
+  static const char* n64[] = {
+      "k_d2q9_lattice<double,64,1,1>",  "k_d2q9_lattice<double,128,1,1>",
+      "k_d2q9_lattice<double,256,1,1>", "k_d2q9_lattice<double,64,4,1>",
+      "k_d2q9_lattice<double,128,2,1>", "k_d2q9_lattice<double,256,1,2>",
+      "k_d2q9_lattice<double,256,1,4>", "k_d2q9_lattice<double,128,2,4>"};
+  if (v < 0 || v >= kNumLat2) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, const void* src, void* dst,
+                                    const LatticeGeom& g, double* partials,
+                                    unsigned long long* bad, hipStream_t s) {
+  if (precision) return lat2_dispatch<float>(v, diag, src, dst, g, partials, bad, s);
+  return lat2_dispatch<double>(v, diag, src, dst, g, partials, bad, s);
+}
+
+int d2q9_num_member_variants() { return kNumMem2; }
+
+hipError_t d2q9_member_kernel(int precision, int v, const void** func, dim3* block) {
+  if (v < 0 || v >= kNumMem2) return hipErrorInvalidValue;
+  *func = precision ? mem2_func<float>(v) : mem2_func<double>(v);
+  *block = dim3(kMem2[v].nt, 1, 1);
+  return hipSuccess;
+}
+
+const char* d2q9_member_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_d2q9_members<float,256,1>", "k_d2q9_members<float,512,1>",
+                              "k_d2q9_members<float,1024,1>", "k_d2q9_members<float,512,2>",
+                              "k_d2q9_members<float,1024,2>"};
+  static const char* n64[] = {"k_d2q9_members<double,256,1>", "k_d2q9_members<double,512,1>",
+                              "k_d2q9_members<double,1024,1>", "k_d2q9_members<double,512,2>",
+                              "k_d2q9_members<double,1024,2>"};
+  if (v < 0 || v >= kNumMem2) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
+                            int n_members, const double* n0, const double* eps0,
+                            const double* u0, int64_t ncells, hipStream_t s) {
+  dim3 grid(grid2_for(ncells));
+  if (precision)
+    hipLaunchKernelGGL(k_d2q9_init<float>, grid, dim3(256), 0, s, (float*)state, cs, descs,
+                       n_members, n0, eps0, u0, ncells);
+  else
+    hipLaunchKernelGGL(k_d2q9_init<double>, grid, dim3(256), 0, s, (double*)state, cs, descs,
+                       n_members, n0, eps0, u0, ncells);
+  return hipGetLastError();
+}
+
+hipError_t d2q9_launch_export(int precision, const void* state, int64_t cs,
+                              const MemberDesc* descs, int n_members, int64_t ncells, double* n,
+                              double* eps, double* P, double* gamma, double* u,
+                              double* partials, int nparts, hipStream_t s) {
+  if (precision)
+    hipLaunchKernelGGL(k_d2q9_export<float>, dim3(nparts), dim3(256), 0, s, (const float*)state,
+                       cs, descs, n_members, ncells, n, eps, P, gamma, u, partials);
+  else
+    hipLaunchKernelGGL(k_d2q9_export<double>, dim3(nparts), dim3(256), 0, s,
+                       (const double*)state, cs, descs, n_members, ncells, n, eps, P, gamma, u,
+                       partials);
+  return hipGetLastError();
+}
+
+hipError_t d2q9_launch_population_planes(int precision, const void* state, int64_t cs,
+                                         const MemberDesc* descs, int n_members, int64_t ncells,
+                                         int p0, int np, double* out, hipStream_t s) {
+  dim3 grid(grid2_for(ncells));
+  if (precision)
+    hipLaunchKernelGGL(k_d2q9_planes<float>, grid, dim3(256), 0, s, (const float*)state, cs,
+                       descs, n_members, ncells, p0, np, out);
+  else
+    hipLaunchKernelGGL(k_d2q9_planes<double>, grid, dim3(256), 0, s, (const double*)state, cs,
+                       descs, n_members, ncells, p0, np, out);
+  return hipGetLastError();
+}
+
+}  // namespace rlb

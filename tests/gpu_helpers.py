@@ -34,6 +34,7 @@ def gpu_state(sim, problems):
     m = sim.moments(allow_unphysical=True)
     f = f.cpu().numpy()
     g = g.cpu().numpy()
+    q = f.shape[0]  # 19 (D3Q19) or 9 (D2Q9)
     out = []
     if not isinstance(problems, (list, tuple)):
         problems = [problems]
@@ -42,7 +43,7 @@ def gpu_state(sim, problems):
         sh = p.params.shape
         nc = p.params.ncells
         sl = slice(off, off + nc)
-        out.append({"f": f[:, sl].reshape((19,) + sh), "g": g[:, sl].reshape((19,) + sh),
+        out.append({"f": f[:, sl].reshape((q,) + sh), "g": g[:, sl].reshape((q,) + sh),
                     "n": m["n"][sl].cpu().numpy().reshape(sh),
                     "eps": m["eps"][sl].cpu().numpy().reshape(sh),
                     "P": m["P"][sl].cpu().numpy().reshape(sh),

@@ -149,3 +149,25 @@ def test_package_fails_loudly_without_gpu():
         pytest.skip("a GPU is visible")
     with pytest.raises(RuntimeError):
         rlb.Simulation([_p()], *_fields(96))
+
+
+def test_d2q9_options_validated():
+    """D2Q9 handles: nz = 1 only, no tape, 18 population planes per buffer."""
+    d2 = rlb.options(rlb.FP32, lattice=rlb.D2Q9)
+    assert _size([_p(nz=3)], d2)[0] == -1
+    assert _size([_p(nx=4, ny=800, nz=1)], rlb.options(rlb.FP32, 50, 100, lattice=rlb.D2Q9))[0] == -7
+    assert _size([_p()], rlb.options(lattice=2))[0] == -1
+    c2, b2 = _size([_p(nx=4096, ny=4096, nz=1, bc=(0, 0, 0))], d2)
+    c3, b3 = _size([_p(nx=4096, ny=4096, nz=1, bc=(0, 0, 0))], rlb.options(rlb.FP32))
+    assert c2 == 0 and c3 == 0
+    assert 2 * 18 * 4 * 4096 ** 2 <= b2 < b3 - 2 * 19 * 4 * 4096 ** 2
+    assert rlb.lattice_code("d2q9") == rlb.D2Q9 and rlb.lattice_code("D3Q19") == rlb.D3Q19
+
+
+def test_d2q9_init_rejects_out_of_plane_velocity():
+    p = _p(nx=6, ny=5, nz=1, bc=(0, 1, 0))
+    opt = rlb.options(rlb.FP32, lattice=rlb.D2Q9)
+    _, need = _size([p], opt)
+    fake = 1 << 40
+    assert _init([p], _fields(30, u=(0.1, 0.0, 0.05)), fake, need, opt) == -3
+    assert _init([_p(nx=6, ny=5, nz=2)], _fields(60), fake, need, opt) == -1

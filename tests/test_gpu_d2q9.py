@@ -1,0 +1,187 @@
+"""GPU parity of the D2Q9 MRT model (Sec. V.A, Eqs. 30-35) against the FP64
+oracle: both dispatch paths (fused per-step lattice kernel, persistent
+per-member kernel), both precisions, ragged tails and mixed boundaries; the
+4 x 800 shock tube of Sec. V.B as a batch of Cases A-D over 400 steps; the
+4096^2 benchmark lattice on sampled cells; conservation and variant identity.
+
+Tolerances (max-norm relative): FP64 1e-12, FP32 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_helpers import compare, gpu_run, gpu_state, relmax, say
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL = {FP64: 1e-12, FP32: 1e-5}
+
+SHAPES = [
+    # (nx, ny, bc): >= 16384 cells take the lattice path, smaller the persistent one
+    (131, 129, (0, 0, 0)),
+    (300, 61, (1, 0, 0)),
+    (37, 29, (0, 1, 0)),
+    (1, 300, (0, 1, 0)),
+    (300, 1, (1, 0, 0)),
+    (70, 259, (1, 1, 0)),
+]
+
+
+def _problem(nx, ny, bc, seed=7, **kw):
+    p = wl.random_modes(nx, ny, 1, seed=seed, umax=0.2, amp=0.1, tau_v=0.8, tau_e=0.55,
+                        tau_eps=0.7, tau_f=0.63, bc=bc)
+    p.params.lattice = "d2q9"
+    p.params.tau_q = kw.get("tau_q", 1.1)
+    return p
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}_bc{s[2]}")
+def test_step_matches_oracle(prec, shape):
+    nx, ny, bc = shape
+    prob = _problem(nx, ny, bc)
+    T = 25
+    say("d2q9 step", prob.name, "bc", bc, "prec", prec)
+    sim = gpu_run(prob, T, prec)
+    say("  kernel", sim.kernel_name)
+    (gs,), sums, bad = gpu_state(sim, prob)
+    st = oracle.run(prob, T)
+    F = st.fields()
+    err = compare(gs, st, F)
+    say("  errors", err)
+    assert gs["f"].shape[0] == 9
+    assert bad == 0 and st.bad == 0
+    assert err["f"] < TOL[prec] and err["g"] < TOL[prec], err
+    assert err["eps"] < TOL[prec] and err["n"] < TOL[prec] and err["u"] < TOL[prec], err
+    assert np.abs(gs["u"][2]).max() == 0.0
+    assert relmax(sums, F["sums"]) < (1e-13 if prec == FP64 else 1e-7)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("shape", [(160, 130, (0, 1, 0)), (45, 38, (1, 0, 0))],
+                         ids=["lattice", "persistent"])
+def test_every_variant_is_identical(prec, shape):
+    import paper_1211_3286_amd as rlb
+    prob = _problem(*shape)
+    ref = None
+    sim0 = rlb.from_problems(prob, precision=prec)
+    names = sim0.variants()
+    sim0.close()
+    for v in range(len(names)):
+        sim = rlb.from_problems(prob, precision=prec)
+        sim.variant = v
+        sim.step(7)
+        f, g = [t.cpu().numpy() for t in sim.populations()]
+        say("variant", names[v])
+        if ref is None:
+            ref = (f, g)
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), names[v]
+        sim.close()
+    st = oracle.run(prob, 7)
+    assert relmax(ref[0].reshape(st.f.shape), st.f) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (FP32, 1e-5)])
+def test_sec5_cases_batch_400_steps(prec, tol):
+    """The four MRT cases of Sec. V.B as one batch (4 members of 4 x 800),
+    400 steps: every member equals the oracle, and a member run alone is
+    bit-identical to the same member in the batch."""
+    import paper_1211_3286_amd as rlb
+    cases = [wl.qgp_tube_2d(c) for c in "ABCD"]
+    sim = rlb.from_problems(cases, precision=prec, diag_every=100)
+    say("cases A-D batch prec", prec, "kernel", sim.kernel_name)
+    sim.step(400)
+    states, sums, bad = gpu_state(sim, cases)
+    assert bad == 0
+    for c, gs in zip(cases, states):
+        st = oracle.run(c, 400)
+        F = st.fields()
+        err = compare(gs, st, F)
+        say("  ", c.name, err)
+        assert err["f"] < tol and err["g"] < tol and err["u"] < tol and err["eps"] < tol, err
+    one = rlb.from_problems(cases[2], precision=prec)
+    one.step(400)
+    (g1,), _, _ = gpu_state(one, cases[2])
+    assert np.array_equal(g1["g"], states[2]["g"]) and np.array_equal(g1["f"], states[2]["f"])
+    s, step, nbad = sim.diagnostics()
+    assert step == 400 and nbad == 0
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_periodic_conservation(prec):
+    prob = _problem(192, 160, (0, 0, 0))
+    sim = gpu_run(prob, 0, prec, diag_every=60)
+    s0 = sim.sums()
+    sim.step(240)
+    s1 = sim.sums()
+    d, step, _ = sim.diagnostics()
+    drift = np.abs(s1 - s0).max() / np.abs(s0[:2]).max()
+    say("d2q9 conservation prec", prec, "drift", drift)
+    # FP32: each cell-update rounds its folded-back residual once (unbiased),
+    # a random walk of about 1e-8 sqrt(T / cells) relative after T steps
+    ncells = prob.params.ncells
+    assert drift < (1e-13 if prec == FP64 else 1e-8 * np.sqrt(240 / ncells))
+    # the diagnostics of step 240 sum the populations streamed into it
+    assert step == 240 and relmax(d, s1) < (1e-13 if prec == FP64 else 1e-10)
+
+
+def test_host_pointer_populations_and_validation():
+    import ctypes
+    import torch
+    import paper_1211_3286_amd as rlb
+    prob = _problem(23, 17, (0, 1, 0))
+    sim = gpu_run(prob, 5, FP64)
+    f = np.zeros((9, prob.params.ncells))
+    g = np.zeros((9, prob.params.ncells))
+    assert rlb.lib().rlb_populations(sim.h, f.ctypes.data, g.ctypes.data, 0) == 0
+    st = oracle.run(prob, 5)
+    assert relmax(f.reshape(st.f.shape), st.f) < 1e-12
+    assert relmax(g.reshape(st.g.shape), st.g) < 1e-12
+    bad = _problem(23, 17, (0, 1, 0))
+    bad.u[2, 0, 3, 4] = 0.01
+    with pytest.raises(rlb.RLBError) as ei:
+        rlb.from_problems(bad)  # device fields: checked by the validation kernel
+    assert ei.value.code == -3
+    del torch
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("prec,tol", [(FP32, 1e-5), (FP64, 1e-12)])
+def test_full_size_4096_squared_sampled(prec, tol):
+    """The 4096 x 4096 periodic benchmark lattice in the autotuned launch
+    configuration, sampled cells checked against the oracle on their light
+    cones (after K steps a cell depends on its (2K+1)^2 neighbourhood)."""
+    import torch
+    import paper_1211_3286_amd as rlb
+    prob = wl.random_modes(4096, 4096, 1, seed=1211, umax=0.1, amp=0.05, tau_v=0.8,
+                           tau_e=0.55, tau_eps=0.7, tau_f=0.8)
+    prob.params.lattice = "d2q9"
+    K = 4
+    sim = rlb.from_problems(prob, precision=prec)
+    res = sim.tune(trial_steps=3)
+    say("4096^2 d2q9 prec", prec, "tuned", res["name"])
+    sim.step(K)
+    f, g = sim.populations()
+    rng = np.random.default_rng(5)
+    cells = [(0, 0, 0), (0, 4095, 4095), (0, 2048, 17)] + [
+        (0, int(rng.integers(4096)), int(rng.integers(4096))) for _ in range(5)]
+    worst = 0.0
+    for c in cells:
+        idx = c[1] * 4096 + c[2]
+        sub, loc = wl.window(prob, c, K)
+        st = oracle.run(sub, K)
+        of = st.f[(slice(None),) + loc]
+        og = st.g[(slice(None),) + loc]
+        scale = max(np.abs(st.f).max(), np.abs(st.g).max())
+        err = max(np.abs(f[:, idx].cpu().numpy() - of).max(),
+                  np.abs(g[:, idx].cpu().numpy() - og).max()) / scale
+        worst = max(worst, err)
+    say("  worst sampled error", worst)
+    assert worst < tol
+    sim.close()
+    del f, g
+    torch.cuda.empty_cache()
