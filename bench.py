@@ -208,14 +208,18 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50):
 def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10):
     """The D2Q9 MRT model of Sec. V.A: an n x n periodic random flow in FP32
     and FP64 (one fused launch per step, 2 x 18 populations per cell update),
-    and the four Sec. V.B cases on 4 x 800 as one persistent batch, 400 steps."""
+    also in FP32 with the correction term of Eqs. (37)-(38) (bytes counted at
+    the same 144 per cell: the neighbour re-reads are cache hits); the four
+    Sec. V.B cases on 4 x 800 as one persistent batch, 400 steps; and the
+    corrected moderately relativistic Cases A and D."""
     prob = wl.random_modes(n, n, 1, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
                            tau_eps=0.7, tau_f=0.8)
     prob.params.lattice = "d2q9"
     cells = prob.params.ncells
     out = {"lattice": f"{n}x{n}x1 periodic", "steps": steps}
-    for prec, name in ((rlb.FP32, "fp32"), (rlb.FP64, "fp64")):
-        sim = rlb.from_problems(prob, precision=prec, diag_every=50)
+    for prec, name, corr in ((rlb.FP32, "fp32", 0), (rlb.FP64, "fp64", 0),
+                             (rlb.FP32, "fp32_c7", 1)):
+        sim = rlb.from_problems(prob, precision=prec, diag_every=50, correction=corr)
         tune = sim.tune(trial_steps=3)
         s0 = sim.sums()
         ms, _ = time_steps(torch, sim, steps, warmup)
@@ -229,9 +233,12 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
         sim.close()
     del prob
     cases = [wl.qgp_tube_2d(c) for c in "ABCD"]
-    nc = sum(c.params.ncells for c in cases)
-    for prec, name in ((rlb.FP64, "cases_A_D_fp64"), (rlb.FP32, "cases_A_D_fp32")):
-        sim = rlb.from_problems(cases, precision=prec)
+    moderate = [wl.qgp_tube_2d(c, a=1.0 / 30.0, moderate=True, correction=True) for c in "AD"]
+    runs = ((rlb.FP64, "cases_A_D_fp64", cases), (rlb.FP32, "cases_A_D_fp32", cases),
+            (rlb.FP64, "moderate_A_D_c7_fp64", moderate))
+    for prec, name, batch in runs:
+        nc = sum(c.params.ncells for c in batch)
+        sim = rlb.from_problems(batch, precision=prec)
         tune = sim.tune(trial_steps=50)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -241,7 +248,7 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        out[name] = {"members": "4 x (4x800), Cases A-D, a = 1/20", "steps": 400,
+        out[name] = {"members": " ".join(c.name for c in batch), "steps": 400,
                      "ms_total": ms, "us_per_step": 1e3 * ms / 400,
                      "mlups": nc * 400 / (ms * 1e-3) / 1e6, "kernel": tune["name"],
                      "inadmissible": sim.moments()["bad"]}

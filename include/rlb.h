@@ -114,6 +114,15 @@ typedef struct {
                           nz = 1 and every input cell u_z = 0 (else RLB_E_ARG,
                           RLB_E_UNPHYSICAL); no tape (ckpt_every > 0 gives
                           RLB_E_UNSUPPORTED). */
+  int32_t correction;  /* 0 or 1 (D2Q9 only, else RLB_E_UNSUPPORTED): add the
+                          correction term of Eqs. (37)-(38) to the p_xx row,
+                          m* = m - S (m - m_eq) + (I - S/2) C, C_7 from central
+                          y-differences of the recovered fields of each cell's
+                          y-neighbours (flows along y, the paper's z). The
+                          printed C_7 belongs to the row e_flow^2 - e_perp^2,
+                          the negative of this basis' e_x^2 - e_y^2, so the
+                          row receives -C_7. No correction next to an
+                          inadmissible cell. */
 } rlb_options;
 
 typedef struct rlb_sim* rlb_handle;

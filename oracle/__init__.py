@@ -54,7 +54,7 @@ def _load():
     lib.oracle_d2q9_collide_cell.argtypes = [P, D, D, D, D]
     lib.oracle_d2q9_collide_cell.restype = ctypes.c_int
     lib.oracle_d2q9_init.argtypes = [P, D, D, D, D, D]
-    lib.oracle_d2q9_step.argtypes = [P, ctypes.c_int32, D, D]
+    lib.oracle_d2q9_step.argtypes = [P, ctypes.c_int32, D, D, ctypes.c_int32]
     lib.oracle_d2q9_step.restype = ctypes.c_int64
     lib.oracle_d2q9_fields.argtypes = [P, D, D, D, D, D, D, D, D]
     lib.oracle_d2q9_fields.restype = ctypes.c_int64
@@ -225,8 +225,14 @@ class State:
 
     def step(self, nsteps: int = 1) -> int:
         cp = cparams(self.params)
-        fn = _load().oracle_d2q9_step if is_d2q9(self.params) else _load().oracle_step
-        bad = fn(ctypes.byref(cp), int(nsteps), _ptr(self.f), _ptr(self.g))
+        if is_d2q9(self.params):
+            corr = int(bool(getattr(self.params, "correction", 0)))
+            bad = _load().oracle_d2q9_step(ctypes.byref(cp), int(nsteps), _ptr(self.f),
+                                           _ptr(self.g), corr)
+        else:
+            if getattr(self.params, "correction", 0):
+                raise ValueError("the correction term of Eqs. (37)-(38) is a D2Q9 option")
+            bad = _load().oracle_step(ctypes.byref(cp), int(nsteps), _ptr(self.f), _ptr(self.g))
         self.t += nsteps
         self.bad += int(bad)
         return int(bad)

@@ -27,6 +27,14 @@
 //     own velocity set, weights, basis (the rows that reproduce Eq. 34),
 //     S of Eq. (31), g_eq of Eqs. (32)-(33), f_eq of Eq. (7)'s form with the
 //     D2Q9 weights, the same recovery, on an nx x ny x 1 lattice.
+//   * The correction term of Eqs. (37)-(38) on that model: C_7 of Eq. (38)
+//     on the row-7 moment through (I - S/2) C, for flows along one axis (the
+//     lattice's y, the paper's z), with central differences for the
+//     derivatives. The printed sign belongs to the row e_flow^2 - e_perp^2;
+//     this basis has row 7 = e_x^2 - e_y^2 with the flow along y, its
+//     negative, so the term enters with a minus sign (a reading that a
+//     Chapman-Enskog expansion of these equilibria confirms: only then does it
+//     cancel the leading error of the row-7 flux; a test checks it).
 //
 // Readings where the paper is silent are listed in the design notes; each one
 // used here is named at its place in the code.
@@ -413,7 +421,7 @@ void moments2(const double f[9], const double g[9], double& N, double& E, double
 // (Eq. 5), g MRT (Eq. 35): m = M g, m_eq = M g_eq, m* = m - S (m - m_eq),
 // g* = M^-1 m*. Returns false (and copies) when the cell is inadmissible.
 bool cell2(const Params& p, const double s[9], const double f[9], const double g[9],
-           double fout[9], double gout[9]) {
+           double fout[9], double gout[9], double c7 = 0.0) {
   double N, E, M[3];
   moments2(f, g, N, E, M);
   Fields<double> F;
@@ -437,12 +445,54 @@ bool cell2(const Params& p, const double s[9], const double f[9], const double g
     double d = conserved_row2(k) ? 0.0 : (m[k] - meq[k]);
     ms[k] = m[k] - s[k] * d;
   }
+  // Eq. (37): m* = m - S (m - m_eq) + (I - S/2) C with C = (0, ..., C_7, 0);
+  // c7 is the correction of this basis' row 7 (see c7_row).
+  ms[7] += (1.0 - 0.5 * s[7]) * c7;
   for (int a = 0; a < 9; ++a) {
     gout[a] = 0.0;
     for (int k = 0; k < 9; ++k) gout[a] += MINV2[a][k] * ms[k];
   }
   return true;
 }
+
+// Fields of a D2Q9 cell from its pre-collision g (Eq. 10 and the recovery).
+bool fields2(const double g[9], Fields<double>& F) {
+  double E = 0.0, M[3] = {0.0, 0.0, 0.0};
+  for (int a = 0; a < 9; ++a) {
+    E += g[a];
+    M[0] += EV2[a][0] * g[a];
+    M[1] += EV2[a][1] * g[a];
+  }
+  return recover<double>(1.0, E, M, F);
+}
+
+// C_7 as printed in Eq. (38) at a cell, the flow axis being y (the paper's
+// z), dt = 1:
+//   C_7 = 2 [u d(c_s^2 sigma - P) - c_s^2 sigma gamma^-1 u d(gamma)
+//            - u d(sigma u^2) + u^2 theta d(sigma u)],
+//   theta = 1 + 1 / ((eps/P + 1) gamma^2 - 1),
+// u = u_y of the cell, d = the central difference (F(y+1) - F(y-1)) / 2 with
+// the neighbours taken by the streaming rule of the y axis (wrap or clamp).
+// Reading: C_7 = 0 when the cell or a neighbour is inadmissible.
+double c7_term(const Fields<double>& F, bool ok, const Fields<double>& Fm, bool okm,
+               const Fields<double>& Fp, bool okp) {
+  if (!ok || !okm || !okp) return 0.0;
+  auto x1 = [](const Fields<double>& G) { return CS2 * G.sigma - G.P; };
+  auto su2 = [](const Fields<double>& G) { return G.sigma * G.u[1] * G.u[1]; };
+  auto su = [](const Fields<double>& G) { return G.sigma * G.u[1]; };
+  const double u = F.u[1];
+  const double theta = 1.0 + 1.0 / ((F.eps / F.P + 1.0) * F.gamma * F.gamma - 1.0);
+  const double d_x1 = 0.5 * (x1(Fp) - x1(Fm));
+  const double d_gam = 0.5 * (Fp.gamma - Fm.gamma);
+  const double d_su2 = 0.5 * (su2(Fp) - su2(Fm));
+  const double d_su = 0.5 * (su(Fp) - su(Fm));
+  return 2.0 * (u * d_x1 - CS2 * F.sigma / F.gamma * u * d_gam - u * d_su2 +
+                u * u * theta * d_su);
+}
+
+// The correction of row 7 = e_x^2 - e_y^2 for a flow along y: the printed
+// term belongs to the row e_flow^2 - e_perp^2 = -(row 7), hence the sign.
+inline double c7_row(double c7_printed) { return -c7_printed; }
 
 inline int64_t src_cell2(const Params& p, int x, int y, int a) {
   int sx = src_coord(x, EV2[a][0], p.nx, p.bc[0]);
@@ -546,34 +596,54 @@ void oracle_d2q9_init(const Params* p, const double* n0, const double* eps0, con
   }
 }
 
-// nsteps D2Q9 time steps in place: pull, sums, recovery, collisions.
-// Returns the number of inadmissible cell-updates.
-int64_t oracle_d2q9_step(const Params* p, int32_t nsteps, double* f, double* g) {
+// nsteps D2Q9 time steps in place: pull, sums, recovery, collisions; with
+// correction != 0 the C_7 term of Eqs. (37)-(38) from the fields of the
+// pulled state. Returns the number of inadmissible cell-updates.
+int64_t oracle_d2q9_step(const Params* p, int32_t nsteps, double* f, double* g,
+                         int32_t correction) {
   build_tables2();
   const int64_t nc = (int64_t)p->nx * p->ny;
   double s[9];
   rates2(*p, s);
-  std::vector<double> fn((size_t)(9 * nc)), gn((size_t)(9 * nc));
+  std::vector<double> fl((size_t)(9 * nc)), gl((size_t)(9 * nc));
+  std::vector<Fields<double>> F((size_t)nc);
+  std::vector<char> ok((size_t)nc);
   int64_t bad = 0;
   for (int t = 0; t < nsteps; ++t) {
+    // streaming (pull) of every cell, then the fields of the pulled state
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < p->ny; ++y)
+      for (int x = 0; x < p->nx; ++x) {
+        int64_t c = (int64_t)y * p->nx + x;
+        double gc[9];
+        for (int a = 0; a < 9; ++a) {
+          int64_t sc = src_cell2(*p, x, y, a);
+          fl[a * nc + c] = f[a * nc + sc];
+          gl[a * nc + c] = gc[a] = g[a * nc + sc];
+        }
+        ok[c] = fields2(gc, F[c]);
+      }
 #pragma omp parallel for schedule(static) reduction(+ : bad)
     for (int y = 0; y < p->ny; ++y)
       for (int x = 0; x < p->nx; ++x) {
         int64_t c = (int64_t)y * p->nx + x;
-        double fl[9], gl[9], fo[9], go[9];
+        double fc[9], gc[9], fo[9], go[9];
         for (int a = 0; a < 9; ++a) {
-          int64_t sc = src_cell2(*p, x, y, a);
-          fl[a] = f[a * nc + sc];
-          gl[a] = g[a * nc + sc];
+          fc[a] = fl[a * nc + c];
+          gc[a] = gl[a * nc + c];
         }
-        if (!cell2(*p, s, fl, gl, fo, go)) ++bad;
+        double c7 = 0.0;
+        if (correction) {
+          int64_t cm = (int64_t)src_coord(y, 1, p->ny, p->bc[1]) * p->nx + x;   // y - 1
+          int64_t cp = (int64_t)src_coord(y, -1, p->ny, p->bc[1]) * p->nx + x;  // y + 1
+          c7 = c7_row(c7_term(F[c], ok[c], F[cm], ok[cm], F[cp], ok[cp]));
+        }
+        if (!cell2(*p, s, fc, gc, fo, go, c7)) ++bad;
         for (int a = 0; a < 9; ++a) {
-          fn[a * nc + c] = fo[a];
-          gn[a * nc + c] = go[a];
+          f[a * nc + c] = fo[a];
+          g[a * nc + c] = go[a];
         }
       }
-    std::memcpy(f, fn.data(), sizeof(double) * 9 * nc);
-    std::memcpy(g, gn.data(), sizeof(double) * 9 * nc);
   }
   return bad;
 }

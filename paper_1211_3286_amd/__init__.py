@@ -56,7 +56,7 @@ class CParams(ctypes.Structure):
 class COptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("ckpt_every", ctypes.c_int32),
                 ("tape_steps", ctypes.c_int32), ("diag_every", ctypes.c_int32),
-                ("lattice", ctypes.c_int32)]
+                ("lattice", ctypes.c_int32), ("correction", ctypes.c_int32)]
 
 
 _lib = None
@@ -134,9 +134,9 @@ def lattice_code(lattice) -> int:
 
 
 def options(precision: int = FP32, ckpt_every: int = 0, tape_steps: int = 0,
-            diag_every: int = 0, lattice=D3Q19) -> COptions:
+            diag_every: int = 0, lattice=D3Q19, correction: int = 0) -> COptions:
     return COptions(int(precision), int(ckpt_every), int(tape_steps), int(diag_every),
-                    lattice_code(lattice))
+                    lattice_code(lattice), int(correction))
 
 
 def workspace_size(members: Sequence, opt: COptions) -> int:
@@ -156,12 +156,14 @@ class Simulation:
 
     ``fields``: (n0, eps0, u0) as float64 torch tensors on the GPU (or numpy
     arrays, copied once). For a batch, pass flat per-member concatenations.
-    ``lattice``: D3Q19 (default) or D2Q9 (or their names).
+    ``lattice``: D3Q19 (default) or D2Q9 (or their names). ``correction``:
+    1 adds the correction term of Eqs. (37)-(38) (D2Q9 only).
     """
 
     def __init__(self, members: Sequence, n0, eps0, u0, precision: int = FP32,
                  ckpt_every: int = 0, tape_steps: int = 0, diag_every: int = 0,
-                 stream=None, device: Optional[int] = None, lattice=D3Q19):
+                 stream=None, device: Optional[int] = None, lattice=D3Q19,
+                 correction: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1211_3286_amd needs a ROCm GPU; none is visible")
@@ -173,7 +175,8 @@ class Simulation:
         self.device = dev
         self.lattice = lattice_code(lattice)
         self.q = 9 if self.lattice == D2Q9 else 19
-        self.opt = options(precision, ckpt_every, tape_steps, diag_every, self.lattice)
+        self.opt = options(precision, ckpt_every, tape_steps, diag_every, self.lattice,
+                           correction)
         self._arr = cparams(self.members)
         self.ws_bytes = workspace_size(self.members, self.opt)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
@@ -343,7 +346,7 @@ class Simulation:
         dev = torch.cuda.get_device_name(self.device)
         shapes = [(int(p.nx), int(p.ny), int(p.nz)) for p in self.members]
         shape = shapes[0] if len(shapes) == 1 else f"{len(shapes)}x{self.ncells}"
-        lat = "d2q9|" if self.lattice == D2Q9 else ""
+        lat = ("d2q9|" if self.lattice == D2Q9 else "") + ("c7|" if self.opt.correction else "")
         return f"{dev}|{lat}{'fp32' if self.precision == FP32 else 'fp64'}|{shape}"
 
 
@@ -365,6 +368,10 @@ def from_problems(problems, **kw) -> Simulation:
     if len(lats) != 1:
         raise ValueError("every member of a batch uses the same lattice model")
     kw.setdefault("lattice", lats.pop())
+    corr = {int(getattr(p.params, "correction", 0)) for p in problems}
+    if len(corr) != 1:
+        raise ValueError("every member of a batch uses the same correction setting")
+    kw.setdefault("correction", corr.pop())
     n, e, u = problem_fields(problems)
     return Simulation([p.params for p in problems], n, e, u, **kw)
 

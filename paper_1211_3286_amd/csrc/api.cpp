@@ -76,6 +76,8 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   if (opt->precision != RLB_FP32 && opt->precision != RLB_FP64) return RLB_E_ARG;
   if (opt->ckpt_every < 0 || opt->tape_steps < 0 || opt->diag_every < 0) return RLB_E_ARG;
   if (opt->lattice != RLB_D3Q19 && opt->lattice != RLB_D2Q9) return RLB_E_ARG;
+  if (opt->correction != 0 && opt->correction != 1) return RLB_E_ARG;
+  if (opt->correction && opt->lattice != RLB_D2Q9) return RLB_E_UNSUPPORTED;
   rlb_status st = check_members(m, n, &L.ncells);
   if (st != RLB_OK) return st;
   const bool d2 = opt->lattice == RLB_D2Q9;
@@ -183,6 +185,7 @@ struct rlb_sim {
   double* d_stage = nullptr;
   int cur = 0;
   bool d2 = false;  // D2Q9 model (9 velocities, 18 planes per buffer)
+  bool corr = false;  // D2Q9 with the correction term of Eqs. (37)-(38)
   int q = 19;
   bool lattice = false;
   LatticeGeom geom{};
@@ -227,8 +230,8 @@ void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
   if (h->d2)
-    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
-                                                 h->d_partials, h->d_bad, h->stream));
+    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, h->corr, src, dst,
+                                                 h->geom, h->d_partials, h->d_bad, h->stream));
   return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
                                           h->d_partials, h->d_bad, h->stream));
 }
@@ -446,7 +449,7 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
     m.partials = h->d_partials;
     m.bad = h->d_bad;
     if (h->d2)
-      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, &func, &block));
+      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, &func, &block));
     else
       RLB_HIP(rlb::member_kernel(h->precision, variant, &func, &block));
     args[0] = &h->margs;
@@ -641,6 +644,7 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->d_flags = (unsigned long long*)(h->ws + L.off_flags);
   h->d_error = (int*)(h->d_small + 24);
   h->d2 = planar;
+  h->corr = opt->correction != 0;
   h->q = nvel(opt->lattice);
   h->lattice = lattice_path(n_members, L.ncells);
   h->variant = h->d2 ? 2 : (h->lattice ? 3 : 2);
@@ -900,7 +904,7 @@ rlb_status rlb_variant_name(rlb_handle h, int32_t v, char* buf, size_t buflen) {
   int32_t n;
   if (rlb_num_variants(h, &n) != RLB_OK || !buf || buflen == 0) return RLB_E_ARG;
   if (v < 0 || v >= n) return RLB_E_ARG;
-  std::snprintf(buf, buflen, "%s", kernel_name_of(h, v));
+  std::snprintf(buf, buflen, "%s%s", kernel_name_of(h, v), h->corr ? "+c7" : "");
   return RLB_OK;
 }
 
@@ -979,7 +983,8 @@ rlb_status rlb_info(rlb_handle h, int64_t* steps, char* kernel_name, size_t bufl
   if (!h) return RLB_E_ARG;
   if (steps) *steps = h->steps;
   if (kernel_name && buflen)
-    std::snprintf(kernel_name, buflen, "%s", kernel_name_of(h, h->variant));
+    std::snprintf(kernel_name, buflen, "%s%s", kernel_name_of(h, h->variant),
+                  h->corr ? "+c7" : "");
   return RLB_OK;
 }
 

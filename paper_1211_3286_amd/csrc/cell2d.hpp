@@ -180,12 +180,16 @@ __device__ __forceinline__ void collide_f(C (&f)[9], double N, double fs, const 
   }
 }
 
-// g: MRT of Eq. (35) in place.
+// g: MRT of Eq. (35) in place; c7 is the correction of Eq. (37) on the
+// p_xx row (0 without it): m*_7 gains (1 - s_v/2) c7.
 template <typename C>
 __device__ __forceinline__ void collide_g(C (&g)[9], double Mx, double My, double gs,
-                                          const Macro& mac, const Rates& rt, const Ref& ref) {
-  d2q9::sub_MT(g, d2q9::scaled_deviation(d2q9::moments_nc(g),
-                                         d2q9::equilibrium_nc<C>(mac, ref), rt));
+                                          const Macro& mac, const Rates& rt, const Ref& ref,
+                                          double c7 = 0.0) {
+  NonConserved<C> c = d2q9::scaled_deviation(d2q9::moments_nc(g),
+                                             d2q9::equilibrium_nc<C>(mac, ref), rt);
+  if (c7 != 0.0) c.pxx = c.pxx - (C)((1.0 - 0.5 * rt.s_v) * c7 * (1.0 / kNormP));
+  d2q9::sub_MT(g, c);
   // FP32 storage: momentum residual into g_1 (x) and g_2 (y), then the
   // energy residual into the rest population, in FP64.
   if constexpr (sizeof(C) == 4) {
@@ -205,10 +209,71 @@ __device__ __forceinline__ void collide_g(C (&g)[9], double Mx, double My, doubl
   }
 }
 
+// ---------------------------------------------------------------------------
+// Correction term of Eqs. (37)-(38) for flows along y (the paper's z):
+//   C_7 = 2 [u d(c_s^2 sigma - P) - c_s^2 sigma gamma^-1 u d(gamma)
+//            - u d(sigma u^2) + u^2 theta d(sigma u)],
+//   theta = 1 + 1 / ((eps/P + 1) gamma^2 - 1),
+// u = u_y, d = central difference (F(y+1) - F(y-1)) / 2 over the neighbours
+// the y-streaming rule picks (wrap or clamp), fields of the pulled state.
+// The printed sign is that of the row e_flow^2 - e_perp^2; this basis' row 7
+// is e_x^2 - e_y^2 = -(that row) for a flow along y, so it gets -C_7. A cell
+// whose neighbour (or itself) is inadmissible gets no correction.
+// ---------------------------------------------------------------------------
+struct C7Fields {
+  double x1, gam, su2, su;  // c_s^2 sigma - P, gamma, sigma u_y^2, sigma u_y
+  bool ok;
+};
+
+__device__ __forceinline__ C7Fields c7_fields(const Macro& m, bool ok) {
+  C7Fields F;
+  F.ok = ok;
+  F.x1 = m.sigma * (1.0 / 3.0) - m.P;
+  F.gam = 1.0 / sqrt(1.0 - m.u2);
+  F.su = m.sigma * m.uy;
+  F.su2 = F.su * m.uy;
+  return F;
+}
+
+// Fields of the cell whose pull offsets are off (its pre-collision g).
+template <typename T>
+__device__ __forceinline__ C7Fields c7_fields_at(const T* __restrict__ src, int64_t cs,
+                                                 const uint32_t (&off)[9], const Ref& ref) {
+  double gd[9];
+#pragma unroll
+  for (int a = 0; a < 9; ++a) gd[a] = (double)ld(src + (int64_t)(9 + a) * cs, off[a]);
+  const double D1 = gd[1] - gd[3], D2 = gd[2] - gd[4], D5 = gd[5] - gd[7], D6 = gd[6] - gd[8];
+  const double gs =
+      gd[0] + ((gd[1] + gd[3]) + (gd[2] + gd[4])) + ((gd[5] + gd[7]) + (gd[6] + gd[8]));
+  Macro m;
+  const bool ok = recover(3.0 * ref.P + gs, D1 + (D5 - D6), D2 + (D5 + D6), 0.0, m);
+  return c7_fields(m, ok);
+}
+
+// Row-7 correction of a cell from its own recovery and its y-neighbours.
+__device__ __forceinline__ double c7_row(const Macro& m, const C7Fields& fm,
+                                         const C7Fields& fp) {
+  if (!fm.ok || !fp.ok) return 0.0;
+  const double u = m.uy;
+  const double gam = 1.0 / sqrt(1.0 - m.u2);
+  const double eps = 0.75 * m.sigma * (1.0 - m.u2);
+  const double theta = 1.0 + 1.0 / ((eps / m.P + 1.0) * gam * gam - 1.0);
+  const double d_x1 = 0.5 * (fp.x1 - fm.x1);
+  const double d_gam = 0.5 * (fp.gam - fm.gam);
+  const double d_su2 = 0.5 * (fp.su2 - fm.su2);
+  const double d_su = 0.5 * (fp.su - fm.su);
+  const double c7 = 2.0 * (u * d_x1 - (1.0 / 3.0) * m.sigma / gam * u * d_gam - u * d_su2 +
+                           u * u * theta * d_su);
+  return -c7;
+}
+
 // One collision of both distributions; false (cell untouched) if inadmissible.
-template <typename C>
+// With CORR, fm / fp are the fields of the y - 1 and y + 1 neighbours and
+// the correction of Eqs. (37)-(38) is applied.
+template <typename C, bool CORR = false>
 __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt, const Ref& ref,
-                                        Sums& sums) {
+                                        Sums& sums, const C7Fields* fm = nullptr,
+                                        const C7Fields* fp = nullptr) {
   double N, E, Mx, My, fs, gs;
   d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
   sums.v[0] = N;
@@ -218,8 +283,10 @@ __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt, c
   sums.v[4] = 0.0;
   Macro mac;
   if (!recover(E, Mx, My, 0.0, mac)) return false;
+  double c7 = 0.0;
+  if constexpr (CORR) c7 = d2q9::c7_row(mac, *fm, *fp);
   d2q9::collide_f(f, N, fs, mac, rt, ref);
-  d2q9::collide_g(g, Mx, My, gs, mac, rt, ref);
+  d2q9::collide_g(g, Mx, My, gs, mac, rt, ref, c7);
   return true;
 }
 

@@ -156,11 +156,13 @@ const char* member_kernel_name(int precision, int variant);
 int d2q9_num_lattice_variants();
 int d2q9_lattice_partials(int variant, const LatticeGeom& g);
 const char* d2q9_lattice_kernel_name(int precision, int variant);
-hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, const void* src,
-                                    void* dst, const LatticeGeom& g, double* partials,
-                                    unsigned long long* bad, hipStream_t s);
+// corr: apply the correction term of Eqs. (37)-(38) (flows along y).
+hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, bool corr,
+                                    const void* src, void* dst, const LatticeGeom& g,
+                                    double* partials, unsigned long long* bad, hipStream_t s);
 int d2q9_num_member_variants();
-hipError_t d2q9_member_kernel(int precision, int variant, const void** func, dim3* block);
+hipError_t d2q9_member_kernel(int precision, int variant, bool corr, const void** func,
+                              dim3* block);
 const char* d2q9_member_kernel_name(int precision, int variant);
 hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
                             int n_members, const double* n0, const double* eps0,

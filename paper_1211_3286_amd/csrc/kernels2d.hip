@@ -16,11 +16,27 @@ namespace rlb {
 
 namespace {
 
+// Fields of the y - 1 and y + 1 neighbours of cell (x, y) for the correction
+// term (their pulled g, recovered), neighbours picked by the y-streaming rule.
+template <typename T>
+__device__ __forceinline__ void c7_neighbours(const T* __restrict__ src, int64_t cs, int x,
+                                              int y, int nx, int ny, int bcx, int bcy,
+                                              uint32_t base, const Ref& ref,
+                                              d2q9::C7Fields& fm, d2q9::C7Fields& fp) {
+  uint32_t off[9], self;
+  d2q9::pull_offsets(x, nbr(y, -1, ny, bcy), nx, ny, bcx, bcy, base, sizeof(T), off, self);
+  fm = d2q9::c7_fields_at(src, cs, off, ref);
+  d2q9::pull_offsets(x, nbr(y, 1, ny, bcy), nx, ny, bcx, bcy, base, sizeof(T), off, self);
+  fp = d2q9::c7_fields_at(src, cs, off, ref);
+}
+
 // -------------------------------------------------------------------------
 // Fused step on one nx x ny lattice: grid (ceil(nx/BX), ceil(ny/(BY*CY))),
-// block (BX, BY); each thread updates CY cells along y.
+// block (BX, BY); each thread updates CY cells along y. CORR adds the
+// correction of Eqs. (37)-(38) (each cell recovers its two y-neighbours from
+// their pulled populations: 18 more loads, mostly L2 hits).
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CY, bool DIAG>
+template <typename T, int BX, int BY, int CY, bool DIAG, bool CORR>
 __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -34,6 +50,10 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
   for (int k = 0; k < CY; ++k) {
     const int y = (blockIdx.y * CY + k) * BY + threadIdx.y;
     if (x < geo.nx && y < geo.ny) {
+      d2q9::C7Fields fm, fp;
+      if constexpr (CORR)
+        c7_neighbours(src, geo.cs, x, y, geo.nx, geo.ny, geo.bcx, geo.bcy, 0u, geo.ref, fm,
+                      fp);
       uint32_t off[9], self;
       d2q9::pull_offsets(x, y, geo.nx, geo.ny, geo.bcx, geo.bcy, 0u, esz, off, self);
       T f[9], g[9];
@@ -43,7 +63,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
         g[a] = ld(src + (int64_t)(9 + a) * geo.cs, off[a]);
       }
       Sums s;
-      const bool ok = d2q9::collide<T>(f, g, geo.rt, geo.ref, s);
+      const bool ok = d2q9::collide<T, CORR>(f, g, geo.rt, geo.ref, s, &fm, &fp);
       nbad += ok ? 0 : 1;
       if (DIAG)
 #pragma unroll
@@ -70,7 +90,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
 // Persistent step over a batch of D2Q9 members: one block per member, all
 // nsteps in the launch with a block barrier between steps.
 // -------------------------------------------------------------------------
-template <typename T, int NT, int CPT>
+template <typename T, int NT, int CPT, bool CORR>
 __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
   const MemberDesc d = a.descs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -91,6 +111,9 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
         if (c < d.ncells) {
           const int y = c / d.nx;
           const int x = c - y * d.nx;
+          d2q9::C7Fields fm, fp;
+          if constexpr (CORR)
+            c7_neighbours(src, a.cs, x, y, d.nx, d.ny, d.bcx, d.bcy, base, d.ref, fm, fp);
           uint32_t off[9], self;
           d2q9::pull_offsets(x, y, d.nx, d.ny, d.bcx, d.bcy, base, esz, off, self);
           T f[9], g[9];
@@ -100,7 +123,7 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
             g[q] = ld(src + (int64_t)(9 + q) * a.cs, off[q]);
           }
           Sums s;
-          const bool ok = d2q9::collide<T>(f, g, d.rt, d.ref, s);
+          const bool ok = d2q9::collide<T, CORR>(f, g, d.rt, d.ref, s, &fm, &fp);
           nbad += ok ? 0 : 1;
 #pragma unroll
           for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
@@ -226,44 +249,44 @@ int grid2_for(int64_t n) {
   return (int)b;
 }
 
-template <typename T, int BX, int BY, int CY>
+template <typename T, int BX, int BY, int CY, bool CORR>
 hipError_t lat2_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                        double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY * CY - 1) / (BY * CY), 1);
   if (diag)
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true>), grid, block, 0, s, (const T*)src,
-                       (T*)dst, g, partials, bad);
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool CORR>
 hipError_t lat2_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
                          double* partials, unsigned long long* bad, hipStream_t s) {
   switch (v) {
-    case 0: return lat2_launch<T, 64, 1, 1>(diag, src, dst, g, partials, bad, s);
-    case 1: return lat2_launch<T, 128, 1, 1>(diag, src, dst, g, partials, bad, s);
-    case 2: return lat2_launch<T, 256, 1, 1>(diag, src, dst, g, partials, bad, s);
-    case 3: return lat2_launch<T, 64, 4, 1>(diag, src, dst, g, partials, bad, s);
-    case 4: return lat2_launch<T, 128, 2, 1>(diag, src, dst, g, partials, bad, s);
-    case 5: return lat2_launch<T, 256, 1, 2>(diag, src, dst, g, partials, bad, s);
-    case 6: return lat2_launch<T, 256, 1, 4>(diag, src, dst, g, partials, bad, s);
-    case 7: return lat2_launch<T, 128, 2, 4>(diag, src, dst, g, partials, bad, s);
+    case 0: return lat2_launch<T, 64, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat2_launch<T, 128, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat2_launch<T, 256, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat2_launch<T, 64, 4, 1, CORR>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat2_launch<T, 128, 2, 1, CORR>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat2_launch<T, 256, 1, 2, CORR>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat2_launch<T, 256, 1, 4, CORR>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat2_launch<T, 128, 2, 4, CORR>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T>
+template <typename T, bool CORR>
 const void* mem2_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_d2q9_members<T, 256, 1>;
-    case 1: return (const void*)&k_d2q9_members<T, 512, 1>;
-    case 2: return (const void*)&k_d2q9_members<T, 1024, 1>;
-    case 3: return (const void*)&k_d2q9_members<T, 512, 2>;
-    case 4: return (const void*)&k_d2q9_members<T, 1024, 2>;
+    case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR>;
+    case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR>;
+    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR>;
+    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR>;
+    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR>;
   }
   return nullptr;
 }
@@ -291,18 +314,24 @@ const char* d2q9_lattice_kernel_name(int precision, int v) {
   return precision ? n32[v] : n64[v];
 }
 
-hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, const void* src, void* dst,
-                                    const LatticeGeom& g, double* partials,
+hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, bool corr, const void* src,
+                                    void* dst, const LatticeGeom& g, double* partials,
                                     unsigned long long* bad, hipStream_t s) {
-  if (precision) return lat2_dispatch<float>(v, diag, src, dst, g, partials, bad, s);
-  return lat2_dispatch<double>(v, diag, src, dst, g, partials, bad, s);
+  if (precision)
+    return corr ? lat2_dispatch<float, true>(v, diag, src, dst, g, partials, bad, s)
+                : lat2_dispatch<float, false>(v, diag, src, dst, g, partials, bad, s);
+  return corr ? lat2_dispatch<double, true>(v, diag, src, dst, g, partials, bad, s)
+              : lat2_dispatch<double, false>(v, diag, src, dst, g, partials, bad, s);
 }
 
 int d2q9_num_member_variants() { return kNumMem2; }
 
-hipError_t d2q9_member_kernel(int precision, int v, const void** func, dim3* block) {
+hipError_t d2q9_member_kernel(int precision, int v, bool corr, const void** func, dim3* block) {
   if (v < 0 || v >= kNumMem2) return hipErrorInvalidValue;
-  *func = precision ? mem2_func<float>(v) : mem2_func<double>(v);
+  if (corr)
+    *func = precision ? mem2_func<float, true>(v) : mem2_func<double, true>(v);
+  else
+    *func = precision ? mem2_func<float, false>(v) : mem2_func<double, false>(v);
   *block = dim3(kMem2[v].nt, 1, 1);
   return hipSuccess;
 }

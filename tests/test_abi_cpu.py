@@ -171,3 +171,10 @@ def test_d2q9_init_rejects_out_of_plane_velocity():
     fake = 1 << 40
     assert _init([p], _fields(30, u=(0.1, 0.0, 0.05)), fake, need, opt) == -3
     assert _init([_p(nx=6, ny=5, nz=2)], _fields(60), fake, need, opt) == -1
+
+
+def test_correction_option_validated():
+    d2 = dict(nx=4, ny=800, nz=1, bc=(0, 1, 0))
+    assert _size([_p(**d2)], rlb.options(lattice=rlb.D2Q9, correction=1))[0] == 0
+    assert _size([_p(**d2)], rlb.options(lattice=rlb.D2Q9, correction=2))[0] == -1
+    assert _size([_p()], rlb.options(correction=1))[0] == -7

@@ -185,3 +185,68 @@ def test_full_size_4096_squared_sampled(prec, tol):
     sim.close()
     del f, g
     torch.cuda.empty_cache()
+
+
+# ---------------------------------------------------------------------------
+# Correction term of Eqs. (37)-(38)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("shape", [(131, 129, (0, 1, 0)), (37, 29, (1, 0, 0)), (1, 300, (0, 1, 0)),
+                                   (300, 61, (0, 0, 0))],
+                         ids=lambda s: f"{s[0]}x{s[1]}_bc{s[2]}")
+def test_corrected_step_matches_oracle(prec, shape):
+    nx, ny, bc = shape
+    prob = _problem(nx, ny, bc)
+    prob.params.correction = 1
+    T = 25
+    sim = gpu_run(prob, T, prec)
+    say("d2q9+c7 step", prob.name, "prec", prec, "kernel", sim.kernel_name)
+    assert sim.kernel_name.endswith("+c7")
+    (gs,), sums, bad = gpu_state(sim, prob)
+    st = oracle.run(prob, T)
+    F = st.fields()
+    err = compare(gs, st, F)
+    say("  errors", err)
+    assert bad == 0 and st.bad == 0
+    assert err["f"] < TOL[prec] and err["g"] < TOL[prec] and err["u"] < TOL[prec], err
+    # the correction changes this flow by far more than the GPU-oracle gap
+    plain = oracle.run(_problem(nx, ny, bc), T)
+    assert relmax(plain.g, st.g) > 100 * max(err["f"], err["g"])
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_corrected_moderate_case_400_steps(prec, tol):
+    """The moderately relativistic tube of Sec. V.B (beta up to about 0.55),
+    Cases A and D with the correction, as one batch, 400 steps."""
+    import paper_1211_3286_amd as rlb
+    cases = [wl.qgp_tube_2d(c, a=1.0 / 30.0, moderate=True, correction=True) for c in "AD"]
+    sim = rlb.from_problems(cases, precision=prec)
+    sim.step(400)
+    states, sums, bad = gpu_state(sim, cases)
+    assert bad == 0
+    for c, gs in zip(cases, states):
+        st = oracle.run(c, 400)
+        F = st.fields()
+        err = compare(gs, st, F)
+        say("  ", c.name, "prec", prec, err)
+        assert err["f"] < tol and err["g"] < tol and err["u"] < tol and err["eps"] < tol, err
+
+
+@pytest.mark.parametrize("shape", [(160, 130, (0, 1, 0)), (45, 38, (1, 1, 0))],
+                         ids=["lattice", "persistent"])
+def test_corrected_variants_identical(shape):
+    import paper_1211_3286_amd as rlb
+    prob = _problem(*shape)
+    prob.params.correction = 1
+    ref = None
+    n = len(rlb.from_problems(prob, precision=FP32).variants())
+    for v in range(n):
+        sim = rlb.from_problems(prob, precision=FP32)
+        sim.variant = v
+        sim.step(6)
+        g = sim.populations()[1].cpu().numpy()
+        if ref is None:
+            ref = g
+        else:
+            assert np.array_equal(g, ref), sim.kernel_name
+        sim.close()

@@ -1,0 +1,155 @@
+"""Oracle pins for the correction term of Eqs. (37)-(38) on the D2Q9 model.
+
+The correction adds (I - S/2) C with C = (0, ..., C_7, 0) to the collision,
+C_7 built from y-derivatives (the flow axis) of the recovered fields. Pins:
+
+* Chapman-Enskog: for a flow along y with uniform u and a density gradient,
+  the first-order flux of row 7 carries an error proportional to u d(sigma)
+  that the correction exists to cancel. The coefficient is derived here with
+  sympy from the D2Q9 equilibria (Eqs. 32-33), independently of Eq. (38),
+  and the change of m_7 that the oracle's correction makes in one step must
+  equal (1 - s_v/2) times it (sign and size).
+* It vanishes where its derivatives vanish: a uniform state stays uniform,
+  and a flow that does not vary along y gives the uncorrected run bit for bit.
+* Homogeneity: every term is of degree one in (sigma, P), so scaling eps and
+  n by 4 scales the corrected populations by 4 exactly.
+* Mirror symmetry about the tube centre (y -> -y, u_y -> -u_y) is kept.
+"""
+
+import numpy as np
+import pytest
+
+import workloads as wl
+
+
+def _tube(L=64, nx=1, bc=(0, 0, 0), correction=1, **tau):
+    t = dict(tau_f=0.7, tau_v=1.3, tau_e=0.8, tau_eps=0.9, tau_q=1.1)
+    t.update(tau)
+    prob = wl.uniform(nx, L, 1, bc=bc, **t)
+    prob.params.lattice = "d2q9"
+    prob.params.correction = correction
+    return prob
+
+
+def _ce_row7_dsigma_coefficient(u0):
+    """Coefficient of d(sigma)/dy in the first-order row-7 term
+    d_t1 m7_eq + d_y F7 of the D2Q9 model, for a 1D flow along y, from a
+    Chapman-Enskog expansion of the equilibria of Eqs. (32)-(33)."""
+    sp = pytest.importorskip("sympy")
+    y = sp.symbols("y")
+    s = sp.Function("sigma")(y)
+    u = sp.Function("u")(y)
+    P = s * (1 - u ** 2) / 4  # P = eps/3, sigma = (eps + P) gamma^2
+    c2 = sp.Rational(1, 3)
+    E = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    W = [sp.Rational(4, 9)] + [sp.Rational(1, 9)] * 4 + [sp.Rational(1, 36)] * 4
+
+    def geq(a):
+        eu = E[a][1] * u
+        if a == 0:
+            return W[0] * s * (sp.Rational(9, 4) - P * (5 + 9 * c2) / (4 * s * c2)
+                               - u ** 2 / (2 * c2))
+        return W[a] * s * (P / (s * c2) + eu / c2 + eu ** 2 / (2 * c2 ** 2) - u ** 2 / (2 * c2))
+
+    g = [geq(a) for a in range(9)]
+    r7 = [ex * ex - ey * ey for ex, ey in E]
+    m7 = sum(r * q for r, q in zip(r7, g))
+    F7 = sum(r * E[a][1] * g[a] for a, r in enumerate(r7))
+    En = sum(g)
+    Mo = sum(E[a][1] * g[a] for a in range(9))
+    Pyy = sum(E[a][1] ** 2 * g[a] for a in range(9))
+    S, U = sp.symbols("S U")
+    J = sp.Matrix([[sp.diff(En.subs({s: S, u: U}), v) for v in (S, U)],
+                   [sp.diff(Mo.subs({s: S, u: U}), v) for v in (S, U)]])
+    rates = J.inv() * sp.Matrix([-sp.diff(Mo, y), -sp.diff(Pyy, y)]).subs({s: S, u: U})
+    m7f = m7.subs({s: S, u: U})
+    dt_m7 = (sp.diff(m7f, S) * rates[0] + sp.diff(m7f, U) * rates[1]).subs({S: s, U: u})
+    D7 = dt_m7 + sp.diff(F7, y)
+    ds, du = sp.symbols("ds du")
+    D7 = D7.subs({sp.Derivative(s, y): ds, sp.Derivative(u, y): du})
+    coef = sp.diff(sp.expand(D7), ds).subs({du: 0})
+    return float(coef.subs({u: u0}))
+
+
+def test_correction_cancels_the_leading_chapman_enskog_error(orc):
+    # small u: the printed term and the expansion differ at O(u^3) (relative
+    # 9 u^2, 0.4 % here), the leading O(u) part must match
+    L, u0, amp = 256, 0.02, 0.01
+    k = 2 * np.pi / L
+    y = np.arange(L)
+    runs = {}
+    for corr in (0, 1):
+        prob = _tube(L, correction=corr, tau_v=1.7)
+        prob.eps[0, :, 0] = 1.0 + amp * np.sin(k * y)
+        prob.u[1] = u0
+        st = orc.run(prob, 1)
+        runs[corr] = st.g.reshape(9, L)
+    M = orc.d2q9_tables()["M"]
+    dm7 = (M @ (runs[1] - runs[0]))[7]
+    # sigma = 4 eps gamma^2 / 3 at uniform u; d(sigma)/dy of the initial field
+    gam2 = 1.0 / (1.0 - u0 * u0)
+    dsig = 4.0 / 3.0 * gam2 * amp * k * np.cos(k * y)
+    want = (1.0 - 0.5 / 1.7) * _ce_row7_dsigma_coefficient(u0) * dsig
+    fit = (dm7 @ want) / (want @ want)
+    assert abs(fit - 1.0) < 0.01, fit
+    assert np.abs(dm7 - want).max() < 0.02 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 1, 0)])
+def test_uniform_state_stays_uniform(orc, bc):
+    prob = _tube(40, nx=3, bc=bc)
+    prob.eps[:] = 1.7
+    prob.u[1] = 0.3
+    prob.u[0] = -0.1
+    st = orc.State.init(prob)
+    f0, g0 = st.f.copy(), st.g.copy()
+    st.step(15)
+    assert np.abs(st.g - g0).max() < 1e-14 * np.abs(g0).max()
+    assert np.abs(st.f - f0).max() < 1e-14 * np.abs(f0).max()
+
+
+def test_no_effect_without_y_variation(orc):
+    """Fields that vary along x only: every y-derivative is zero, so the
+    corrected and uncorrected runs are identical bit for bit."""
+    out = []
+    for corr in (0, 1):
+        prob = _tube(6, nx=48, bc=(0, 1, 0), correction=corr)
+        x = np.arange(48)
+        prob.eps[0] = 1.0 + 0.2 * np.sin(2 * np.pi * x / 48)[None, :]
+        prob.u[1, 0] = 0.2 * np.cos(2 * np.pi * x / 48)[None, :]
+        out.append(orc.run(prob, 20).g)
+    assert np.array_equal(out[0], out[1])
+
+
+def test_correction_changes_a_flow_along_y(orc):
+    out = []
+    for corr in (0, 1):
+        prob = _tube(64, correction=corr)
+        prob.eps[0, :, 0] = 1.0 + 0.3 * np.sin(2 * np.pi * np.arange(64) / 64)
+        prob.u[1] = 0.2
+        out.append(orc.run(prob, 20).g)
+    assert np.abs(out[0] - out[1]).max() > 1e-6 * np.abs(out[0]).max()
+
+
+def test_homogeneous_of_degree_one(orc):
+    base = wl.qgp_tube_2d("D", moderate=True, a=1.0 / 30.0, correction=True, length=200)
+    scaled = wl.qgp_tube_2d("D", moderate=True, a=1.0 / 30.0, correction=True, length=200)
+    scaled.eps = 4.0 * base.eps
+    scaled.n = 4.0 * base.n
+    a = orc.run(base, 60)
+    b = orc.run(scaled, 60)
+    assert np.array_equal(4.0 * a.g, b.g) and np.array_equal(4.0 * a.f, b.f)
+
+
+def test_mirror_symmetry(orc):
+    L = 120
+    yc = (L - 1) / 2.0
+    y = np.arange(L) - yc
+    prob = _tube(L, nx=2, bc=(0, 1, 0), tau_v=3.0, tau_e=0.9, tau_eps=0.9, tau_q=3.0)
+    prob.eps[0] = (1.0 + 0.5 * np.exp(-(y / 12.0) ** 2))[:, None]
+    prob.u[1, 0] = (0.3 * np.tanh(y / 10.0))[:, None]
+    st = orc.run(prob, 50)
+    F = st.fields()
+    eps, uy = F["eps"][0, :, 0], F["u"][1, 0, :, 0]
+    assert np.abs(eps - eps[::-1]).max() < 1e-12 * eps.max()
+    assert np.abs(uy + uy[::-1]).max() < 1e-12

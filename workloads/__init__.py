@@ -51,6 +51,7 @@ class Params:
     tau_eps: float = 0.9
     tau_q: float = 0.0  # <= 0: ghost moments relax with tau_v
     lattice: str = "d3q19"  # or "d2q9" (nx x ny x 1, velocities in the x-y plane)
+    correction: int = 0  # D2Q9: 1 adds the C_7 term of Eqs. (37)-(38) (flow along y)
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -302,7 +303,7 @@ def case_taus(case: str, tau_v: float, a: float) -> Dict[str, float]:
 
 def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
                 tau_f: float = 0.6, nx: int = 4, length: int = 800, moderate: bool = False,
-                width: float = 1.0) -> Problem:
+                width: float = 1.0, correction: bool = False) -> Problem:
     """D2Q9 shock tube of Sec. V.B on nx x length x 1 cells.
 
     x is periodic (nx = 4 cells), the long axis y stands for the paper's z
@@ -311,6 +312,7 @@ def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
     at T = 0.0314; ``moderate``: the moderately relativistic case (P_R =
     1.557e-8, T_L / T_R = 0.0359 / 0.018). n = P / T, u = 0. Relaxation times
     from ``case_taus``; tau_v = 100 stands for the paper's "about 100".
+    ``correction`` adds the C_7 term of Eqs. (37)-(38) (the corrected runs).
     """
     st = QGP_MODERATE if moderate else QGP_WEAK
     y = np.arange(length, dtype=np.float64)
@@ -320,11 +322,12 @@ def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
     shape = (1, length, nx)
     t = case_taus(case, tau_v, a)
     prm = Params(nx, length, 1, (PERIODIC, ZERO_GRADIENT, PERIODIC), tau_f, t["tau_v"],
-                 t["tau_e"], t["tau_eps"], t["tau_q"], "d2q9")
+                 t["tau_e"], t["tau_eps"], t["tau_q"], "d2q9", int(bool(correction)))
     ones = np.ones((1, 1, nx))
     return Problem(prm, (n[None, :, None] * ones).copy(), (3.0 * P[None, :, None] * ones).copy(),
                    np.zeros((3,) + shape),
-                   name=f"qgp_tube_2d_{nx}x{length}_case{case}" + ("_moderate" if moderate else ""),
+                   name=f"qgp_tube_2d_{nx}x{length}_case{case}" + ("_moderate" if moderate else "")
+                   + ("_c7" if correction else ""),
                    meta={"case": case, "a": a})
 
 
@@ -371,7 +374,8 @@ def window(problem: Problem, center: Tuple[int, int, int], half: int):
             sub_bc.append(ZERO_GRADIENT)
     iz, iy, ix = np.ix_(*idx)
     sub = Params(len(idx[2]), len(idx[1]), len(idx[0]), (sub_bc[2], sub_bc[1], sub_bc[0]),
-                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q, prm.lattice)
+                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q, prm.lattice,
+                 prm.correction)
     u = np.stack([problem.u[c][iz, iy, ix] for c in range(3)])
     return (Problem(sub, problem.n[iz, iy, ix].copy(), problem.eps[iz, iy, ix].copy(), u,
                     name=problem.name + "_window"), tuple(loc))
