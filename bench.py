@@ -10,8 +10,9 @@ every step. One timed step = one fused kernel launch over all 16.8M cells.
 Also reported ("forms"): the same step in FP64, the batched persistent
 launch over 64 ragged shock tubes (3000 steps, one graph launch), the
 adjoint gradient of a 512 x 512 run (1000 steps, checkpoints every 50), the
-512^3 blast, and the D2Q9 MRT model of Sec. V (a 4096^2 lattice and the
-4 x 800 Cases A-D batch).
+512^3 blast, the D2Q9 MRT model of Sec. V (a 4096^2 lattice, the
+4 x 800 Cases A-D batch, the correction of Eqs. 37-38), and relaxation times
+set per cell from eta/s.
 
 Prints one JSON line. ``value`` is MLUPS (million lattice-cell updates per
 second) with the populations resident in HBM; ``roofline`` prices the fused
@@ -26,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -256,6 +258,39 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
     return out
 
 
+def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
+    """Relaxation times per cell from eta/s (Sec. III.B): the fused D3Q19 step
+    built for it on the n^3 random flow (FP32), and the Sec. III.B tube with
+    its three tau_f choices as one batch, 400 steps (FP64)."""
+    prob = wl.random_modes(n, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    prob.params.eta_s, prob.params.a_e, prob.params.a_eps = 0.1, 0.2, 0.5
+    sim = rlb.from_problems(prob, precision=rlb.FP32, diag_every=50)
+    tune = sim.tune(trial_steps=3)
+    ms, _ = time_steps(torch, sim, steps, warmup)
+    cells = prob.params.ncells
+    gbs = 304 * cells / (ms * 1e-3) / 1e9
+    out = {"lattice": f"{n}^3 FP32, eta/s = 0.1", "ms_per_step": ms,
+           "mlups": cells / (ms * 1e-3) / 1e6, "kernel": tune["name"], "achieved_gbs": gbs,
+           "frac": gbs / HBM_PEAK_GBS}
+    sim.close()
+    del prob
+    tubes = [wl.qgp_tube_3d(0.1, tau_f=tf) for tf in ("tau_g", 1.0, 0.6)]
+    sim = rlb.from_problems(tubes, precision=rlb.FP64)
+    tune = sim.tune(trial_steps=20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(400)
+    e1.record()
+    torch.cuda.synchronize()
+    out["sec3_tube_batch"] = {"members": "3 x (1x1x800), tau_f = tau_g, 1.0, 0.6", "steps": 400,
+                              "ms_total": e0.elapsed_time(e1), "kernel": tune["name"]}
+    sim.close()
+    return out
+
+
 def cpu_baseline(prob, seconds: float):
     """The FP64 oracle on the host cores, on whole steps of the same lattice."""
     import oracle
@@ -331,10 +366,10 @@ def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict
     scale = {c: (1 << 30) / copy[c] for c in copy}
     out = {"_calibration": {"copy_bytes": 1 << 30, "counter_bytes": copy, "scale": scale}}
     for (k, g, c), v in vals.items():
-        if "k_step_lattice" not in k:
+        if "k_step_lattice" not in k or ", true>" in k:  # the eta/s kernels are not priced
             continue
         name = k.replace("void rlb::(anonymous namespace)::", "").split("(")[0]
-        name = name.replace(", ", ",").replace(",true>", ">").replace(",false>", ">")
+        name = re.sub(r"(,(true|false))+>", ">", name.replace(", ", ","))
         rec = out.setdefault(name, {"cells": cells, "source_hash": kernel_hash()})
         rec[c.lower() + "_bytes"] = sum(v) / len(v) * scale[c]
     for name, rec in out.items():
@@ -415,6 +450,8 @@ def main():
         log("blast", forms["blast_512"])
         forms["d2q9"] = bench_d2q9(torch, rlb, wl)
         log("d2q9", forms["d2q9"])
+        forms["eta_s"] = bench_eta_s(torch, rlb, wl)
+        log("eta_s", forms["eta_s"])
     if args.copy_calibration:
         forms["copy_calibration"] = copy_calibration(torch)
         log("copy", forms["copy_calibration"])

@@ -97,6 +97,20 @@ typedef struct {
   double tau_eps;      /* energy-square row eps, Eq. (31) */
   double tau_q;        /* ghost rows (q, 3pi_xx, pi_ww, m; D2Q9: the q rows of
                           Eq. 31); <= 0 means tau_q = tau_v */
+  /* Relaxation times from the ratio eta/s, cell by cell and step by step
+   * (Sec. III.B), when eta_over_s > 0 (0 = off, the fixed taus above apply):
+   *   T = P / n (ideal gas), n_eq = dof T^3 / pi^2, s = 4n - n ln(n / n_eq),
+   *   tau_v = 1/2 + kappa (eta/s) s / (c_s^2 (eps + P) gamma)
+   * (the viscosity relation after Eq. 10 solved for tau, kappa the shear-
+   * viscosity transformation of Secs. IV and V.A, 1 = none), and for x in
+   * {f, e, eps, q} with a_x > 0: tau_x - 1/2 = a_x (tau_v - 1/2); tau_q <= 0
+   * ties tau_q to the local tau_v. A cell with n <= 0 or P <= 0 uses the
+   * fixed taus, which must be valid in any case. Not with a tape, tube rounds
+   * or segmented launches (RLB_E_UNSUPPORTED). */
+  double eta_over_s;   /* >= 0 */
+  double kappa;        /* > 0 when eta_over_s > 0 */
+  double dof;          /* degeneracy d_G > 0 (16 for gluons) */
+  double a_f, a_e, a_eps, a_q;  /* >= 0 */
 } rlb_params;
 
 typedef struct {

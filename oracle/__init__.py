@@ -29,7 +29,10 @@ class CParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc", ctypes.c_int32 * 3), ("tau_f", ctypes.c_double),
                 ("tau_v", ctypes.c_double), ("tau_e", ctypes.c_double),
-                ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double)]
+                ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double),
+                ("eta_s", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("dof", ctypes.c_double), ("a_f", ctypes.c_double), ("a_e", ctypes.c_double),
+                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double)]
 
 
 _lib = None
@@ -51,6 +54,8 @@ def _load():
     lib.oracle_d2q9_geq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_d2q9_feq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_d2q9_rates.argtypes = [P, D]
+    lib.oracle_cell_taus.argtypes = [P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, D]
     lib.oracle_d2q9_collide_cell.argtypes = [P, D, D, D, D]
     lib.oracle_d2q9_collide_cell.restype = ctypes.c_int
     lib.oracle_d2q9_init.argtypes = [P, D, D, D, D, D]
@@ -102,6 +107,11 @@ def cparams(p) -> CParams:
         c.bc[i] = int(p.bc[i])
     c.tau_f, c.tau_v, c.tau_e = float(p.tau_f), float(p.tau_v), float(p.tau_e)
     c.tau_eps, c.tau_q = float(p.tau_eps), float(p.tau_q)
+    c.eta_s = float(getattr(p, "eta_s", 0.0))
+    c.kappa = float(getattr(p, "kappa", 1.0))
+    c.dof = float(getattr(p, "dof", 16.0))
+    for k in ("a_f", "a_e", "a_eps", "a_q"):
+        setattr(c, k, float(getattr(p, k, 0.0)))
     return c
 
 
@@ -179,6 +189,18 @@ def rates(p) -> np.ndarray:
     fn = _load().oracle_d2q9_rates if q == 9 else _load().oracle_rates
     fn(ctypes.byref(cp), _ptr(out))
     return out
+
+
+def cell_taus(p, n: float, P: float, gamma: float = 1.0, sigma=None) -> Dict[str, float]:
+    """Relaxation times of a cell with fields (n, P, gamma, sigma); sigma
+    defaults to the P = eps/3 value 4 P gamma^2."""
+    out = np.zeros(5)
+    if sigma is None:
+        sigma = 4.0 * P * gamma * gamma
+    cp = cparams(p)
+    _load().oracle_cell_taus(ctypes.byref(cp), float(n), float(P), float(gamma), float(sigma),
+                             _ptr(out))
+    return dict(zip(["tau_f", "tau_v", "tau_e", "tau_eps", "tau_q"], out.tolist()))
 
 
 def collide_cell(p, f, g):
@@ -274,6 +296,8 @@ def grad(problem, nsteps: int, dL_du: np.ndarray, dL_deps: np.ndarray):
     cp = cparams(p)
     args = [np.ascontiguousarray(a, dtype=np.float64)
             for a in (problem.n, problem.eps, problem.u, dL_du, dL_deps)]
-    _load().oracle_grad(ctypes.byref(cp), int(nsteps), *[_ptr(a) for a in args], _ptr(dtau),
-                        _ptr(de0), _ptr(du0))
+    code = _load().oracle_grad(ctypes.byref(cp), int(nsteps), *[_ptr(a) for a in args],
+                               _ptr(dtau), _ptr(de0), _ptr(du0))
+    if code != 0:
+        raise ValueError("the adjoint oracle covers fixed relaxation times only")
     return dtau, de0, du0

@@ -161,6 +161,8 @@ struct Params {
   int32_t nx, ny, nz;
   int32_t bc[3];  // 0 periodic, 1 zero-gradient
   double tau_f, tau_v, tau_e, tau_eps, tau_q;
+  // Relaxation times from eta/s per cell (off when eta_s <= 0), see cell_taus.
+  double eta_s, kappa, dof, a_f, a_e, a_eps, a_q;
 };
 
 // Diagonal of S (Eq. 31 generalised to D3Q19). tau_sigma = tau_j = dt for the
@@ -325,6 +327,42 @@ inline int64_t src_cell(const Params& p, int x, int y, int z, int a) {
 double tau_q_of(const Params& p) { return p.tau_q > 0.0 ? p.tau_q : p.tau_v; }
 
 // ---------------------------------------------------------------------------
+// Relaxation times of one cell. With eta_s > 0 they follow from the ratio of
+// shear viscosity to entropy density, cell by cell (Sec. III.B):
+//   T = P / n (the ideal-gas relation n = P/T of the initial states),
+//   n_eq = d_G T^3 / pi^2, lambda = n / n_eq, s = 4n - n ln(lambda),
+//   eta = (eta/s) s,
+// and the viscosity relation after Eq. (10), eta = (tau - dt/2) c_s^2
+// (eps + P) gamma, solved for tau, scaled by kappa (the transformation of the
+// shear viscosity that Secs. IV and V.A call for; kappa = 1 is the plain
+// relation): tau_v = 1/2 + kappa eta / (c_s^2 (eps + P) gamma).
+// Each of tau_f, tau_e, tau_eps, tau_q with a_x > 0 follows as
+// tau_x - 1/2 = a_x (tau_v - 1/2) (the parameterisation of the Cases of
+// Sec. V.B); the others keep their fixed values. A cell with n <= 0 or P <= 0
+// (no temperature) keeps the fixed values (a reading).
+// ---------------------------------------------------------------------------
+struct Taus {
+  double f, v, e, eps, q;
+};
+
+Taus cell_taus(const Params& p, double n, double P, double gamma, double sigma) {
+  Taus t{p.tau_f, p.tau_v, p.tau_e, p.tau_eps, tau_q_of(p)};
+  if (!(p.eta_s > 0.0) || !(n > 0.0) || !(P > 0.0)) return t;
+  const double T = P / n;
+  const double n_eq = p.dof * T * T * T / (M_PI * M_PI);
+  const double s_dens = 4.0 * n - n * std::log(n / n_eq);
+  const double eta = p.eta_s * s_dens;
+  const double eps_plus_P_gamma = sigma / gamma;  // (eps + P) gamma^2 / gamma
+  t.v = 0.5 + p.kappa * eta / (CS2 * eps_plus_P_gamma);
+  if (p.tau_q <= 0.0) t.q = t.v;
+  if (p.a_f > 0.0) t.f = 0.5 + p.a_f * (t.v - 0.5);
+  if (p.a_e > 0.0) t.e = 0.5 + p.a_e * (t.v - 0.5);
+  if (p.a_eps > 0.0) t.eps = 0.5 + p.a_eps * (t.v - 0.5);
+  if (p.a_q > 0.0) t.q = 0.5 + p.a_q * (t.v - 0.5);
+  return t;
+}
+
+// ---------------------------------------------------------------------------
 // D2Q9 lattice of Sec. V.A. Velocities: rest, (1,0), (0,1), (-1,0), (0,-1),
 // (1,1), (-1,1), (-1,-1), (1,-1) in the (x, y) plane of an nx x ny x 1
 // lattice; weights 4/9, 1/9, 1/36 (c_s^2 = 1/3). The moment basis is the
@@ -420,7 +458,7 @@ void moments2(const double f[9], const double g[9], double& N, double& E, double
 // One D2Q9 cell: recovery (same root as D3Q19, Eq. 10 with P = eps/3), f BGK
 // (Eq. 5), g MRT (Eq. 35): m = M g, m_eq = M g_eq, m* = m - S (m - m_eq),
 // g* = M^-1 m*. Returns false (and copies) when the cell is inadmissible.
-bool cell2(const Params& p, const double s[9], const double f[9], const double g[9],
+bool cell2(const Params& p, const double s_fixed[9], const double f[9], const double g[9],
            double fout[9], double gout[9], double c7 = 0.0) {
   double N, E, M[3];
   moments2(f, g, N, E, M);
@@ -432,9 +470,22 @@ bool cell2(const Params& p, const double s[9], const double f[9], const double g
     }
     return false;
   }
+  double s[9];
+  double tau_f = p.tau_f;
+  for (int k = 0; k < 9; ++k) s[k] = s_fixed[k];
+  if (p.eta_s > 0.0) {  // relaxation times of this cell from eta/s
+    const Taus t = cell_taus(p, F.n, F.P, F.gamma, F.sigma);
+    Params q = p;
+    q.tau_v = t.v;
+    q.tau_e = t.e;
+    q.tau_eps = t.eps;
+    q.tau_q = t.q;
+    rates2(q, s);
+    tau_f = t.f;
+  }
   double feq[9], geq[9], m[9], meq[9], ms[9];
   f_equilibrium2(F.n * F.gamma, F.u, feq);
-  for (int a = 0; a < 9; ++a) fout[a] = f[a] - (f[a] - feq[a]) / p.tau_f;
+  for (int a = 0; a < 9; ++a) fout[a] = f[a] - (f[a] - feq[a]) / tau_f;
   g_equilibrium2(F.sigma, F.P, F.u, geq);
   for (int k = 0; k < 9; ++k) {
     m[k] = meq[k] = 0.0;
@@ -564,6 +615,18 @@ void oracle_d2q9_feq(double n, double gamma, const double* u, double* feq) {
 }
 
 void oracle_d2q9_rates(const Params* p, double* s) { rates2(*p, s); }
+
+// Relaxation times {tau_f, tau_v, tau_e, tau_eps, tau_q} of a cell with fields
+// (n, P, gamma, sigma) under the member's parameters (cell_taus).
+void oracle_cell_taus(const Params* p, double n, double P, double gamma, double sigma,
+                      double* out) {
+  const Taus t = cell_taus(*p, n, P, gamma, sigma);
+  out[0] = t.f;
+  out[1] = t.v;
+  out[2] = t.e;
+  out[3] = t.eps;
+  out[4] = t.q;
+}
 
 // Collision of one D2Q9 cell. Returns 1 if the cell was admissible.
 int oracle_d2q9_collide_cell(const Params* p, const double* f, const double* g, double* fout,
@@ -735,9 +798,10 @@ int oracle_collide_cell(const Params* p, const double* f, const double* g, doubl
     }
     return 0;
   }
+  const Taus t = cell_taus(*p, F.n, F.P, F.gamma, F.sigma);
   double s[19];
-  rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), s);
-  collide_f<double>(f, F, p->tau_f, fout);
+  rates<double>(t.v, t.e, t.eps, t.q, s);
+  collide_f<double>(f, F, t.f, fout);
   collide_g<double>(g, F, s, gout);
   return 1;
 }
@@ -796,6 +860,12 @@ int64_t oracle_step(const Params* p, int32_t nsteps, double* f, double* g) {
               fo[a] = fl[a];
               go[a] = gl[a];
             }
+          } else if (p->eta_s > 0.0) {  // relaxation times of this cell from eta/s
+            const Taus t = cell_taus(*p, F.n, F.P, F.gamma, F.sigma);
+            double sl[19];
+            rates<double>(t.v, t.e, t.eps, t.q, sl);
+            collide_f<double>(fl, F, t.f, fo);
+            collide_g<double>(gl, F, sl, go);
           } else {
             collide_f<double>(fl, F, p->tau_f, fo);
             collide_g<double>(gl, F, s, go);
@@ -896,6 +966,7 @@ static void rates_c(const Params& p, int which, cplx s[19]) {
 int oracle_grad(const Params* p, int32_t nsteps, const double* n0, const double* eps0,
                 const double* u0, const double* dL_du, const double* dL_deps, double* dL_dtau,
                 double* dL_deps0, double* dL_du0) {
+  if (p->eta_s > 0.0) return -1;  // fixed relaxation times only
   build_tables();
   (void)cell_g_real;
   const int64_t nc = (int64_t)p->nx * p->ny * p->nz;

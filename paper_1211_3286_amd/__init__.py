@@ -50,7 +50,10 @@ class CParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
                 ("bc", ctypes.c_int32 * 3), ("tau_f", ctypes.c_double),
                 ("tau_v", ctypes.c_double), ("tau_e", ctypes.c_double),
-                ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double)]
+                ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double),
+                ("eta_over_s", ctypes.c_double), ("kappa", ctypes.c_double),
+                ("dof", ctypes.c_double), ("a_f", ctypes.c_double), ("a_e", ctypes.c_double),
+                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double)]
 
 
 class COptions(ctypes.Structure):
@@ -123,6 +126,11 @@ def cparams(members: Sequence) -> ctypes.Array:
             c.bc[k] = int(p.bc[k])
         c.tau_f, c.tau_v, c.tau_e = float(p.tau_f), float(p.tau_v), float(p.tau_e)
         c.tau_eps, c.tau_q = float(p.tau_eps), float(getattr(p, "tau_q", 0.0))
+        c.eta_over_s = float(getattr(p, "eta_s", 0.0))
+        c.kappa = float(getattr(p, "kappa", 1.0))
+        c.dof = float(getattr(p, "dof", 16.0))
+        for k in ("a_f", "a_e", "a_eps", "a_q"):
+            setattr(c, k, float(getattr(p, k, 0.0)))
     return arr
 
 

@@ -59,6 +59,13 @@ rlb_status check_members(const rlb_params* m, int32_t n, int64_t* ncells) {
       return RLB_E_TAU;
     if (p.tau_q > 0.0 && !finite_tau(p.tau_q)) return RLB_E_TAU;
     if (std::isnan(p.tau_q)) return RLB_E_TAU;
+    if (!std::isfinite(p.eta_over_s) || p.eta_over_s < 0.0) return RLB_E_ARG;
+    if (p.eta_over_s > 0.0) {
+      if (!std::isfinite(p.kappa) || !(p.kappa > 0.0)) return RLB_E_ARG;
+      if (!std::isfinite(p.dof) || !(p.dof > 0.0)) return RLB_E_ARG;
+      for (double a : {p.a_f, p.a_e, p.a_eps, p.a_q})
+        if (!std::isfinite(a) || a < 0.0) return RLB_E_ARG;
+    }
   }
   *ncells = tot;
   return RLB_OK;
@@ -87,6 +94,7 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
     if (opt->ckpt_every > 0) return RLB_E_UNSUPPORTED;  // the adjoint covers D3Q19
   }
   if (opt->ckpt_every > 0 && n != 1) return RLB_E_UNSUPPORTED;
+  if (opt->ckpt_every > 0 && m[0].eta_over_s > 0.0) return RLB_E_UNSUPPORTED;
   L.esz = opt->precision == RLB_FP32 ? 4 : 8;
   // Plane stride: a multiple of 64 elements plus 64 more, so that planes of a
   // power-of-two lattice do not all start on the same HBM channel (measured:
@@ -186,6 +194,7 @@ struct rlb_sim {
   int cur = 0;
   bool d2 = false;  // D2Q9 model (9 velocities, 18 planes per buffer)
   bool corr = false;  // D2Q9 with the correction term of Eqs. (37)-(38)
+  bool lt = false;    // some member takes its relaxation times from eta/s per cell
   int q = 19;
   bool lattice = false;
   LatticeGeom geom{};
@@ -230,9 +239,10 @@ void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
   if (h->d2)
-    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, h->corr, src, dst,
-                                                 h->geom, h->d_partials, h->d_bad, h->stream));
-  return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, src, dst, h->geom,
+    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, h->corr, h->lt,
+                                                 src, dst, h->geom, h->d_partials, h->d_bad,
+                                                 h->stream));
+  return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, h->lt, src, dst, h->geom,
                                           h->d_partials, h->d_bad, h->stream));
 }
 
@@ -306,7 +316,7 @@ rlb_status build_tube_segments(rlb_sim* h, int tv) {
 rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
                         int diag_every, int64_t step0, bool* flip) {
   const int tv = tube_index(variant);
-  if (!h->all_tubes) return RLB_E_UNSUPPORTED;
+  if (!h->all_tubes || h->lt) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
   if (h->seg_built != 1000 + tv) {
     rlb_status st = build_tube_segments(h, tv);
     if (st != RLB_OK) return st;
@@ -414,6 +424,7 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
   dim3 block, grid;
   void* args[1];
   if (is_segment_variant(h, variant)) {
+    if (h->lt) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
     const int sv = variant - rlb::num_member_variants();
     RLB_HIP(rlb::segment_kernel(h->precision, sv, &func, &block));
     rlb_status st = segments_fit(h, sv, func, block.x);
@@ -449,9 +460,9 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
     m.partials = h->d_partials;
     m.bad = h->d_bad;
     if (h->d2)
-      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, &func, &block));
+      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, h->lt, &func, &block));
     else
-      RLB_HIP(rlb::member_kernel(h->precision, variant, &func, &block));
+      RLB_HIP(rlb::member_kernel(h->precision, variant, h->lt, &func, &block));
     args[0] = &h->margs;
     grid = dim3(h->n_members, 1, 1);
   }
@@ -677,6 +688,15 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     d.rt.s_eps = 1.0 / p.tau_eps;
     d.rt.s_q = 1.0 / tq;
     d.rt.s_v = 1.0 / p.tau_v;
+    d.vis.eta_s = p.eta_over_s;
+    d.vis.kappa = p.kappa;
+    d.vis.dof = p.dof;
+    d.vis.a_f = p.a_f;
+    d.vis.a_e = p.a_e;
+    d.vis.a_eps = p.a_eps;
+    d.vis.a_q = p.a_q;
+    d.vis.q_tied = p.tau_q > 0.0 ? 0 : 1;
+    if (p.eta_over_s > 0.0) h->lt = true;
     off += d.ncells;
   }
   const double *dn, *de, *du;
@@ -728,6 +748,7 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     h->geom.cs = L.cs;
     h->geom.rt = d.rt;
     h->geom.ref = d.ref;
+    h->geom.vis = d.vis;
   }
   h->cur = 0;
   if (opt->ckpt_every > 0) {

@@ -39,6 +39,17 @@ struct Rates {
   double s_v;    // 1/tau_v   (3p_xx, p_ww, p_xy, p_yz, p_xz rows)
 };
 
+// Parameters of relaxation times set per cell from eta/s (local_rates); only
+// the kernels built for it read them.
+struct Visc {
+  double eta_s;  // > 0: tau_v of each cell from eta/s (Rates are the fallback)
+  double kappa;  // shear-viscosity transformation factor
+  double dof;    // degeneracy d_G of n_eq = d_G T^3 / pi^2
+  double a_f, a_e, a_eps, a_q;  // > 0: tau_x - 1/2 = a_x (tau_v - 1/2)
+  int32_t q_tied;               // tau_q follows tau_v (tau_q <= 0 given)
+  int32_t pad;
+};
+
 // Rest reference state the populations are stored relative to.
 struct Ref {
   double n;  // n_r
@@ -129,6 +140,36 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
   m.sigma = 4.0 * Es / (3.0 + m.u2);
   m.P = 0.25 * m.sigma * (1.0 - m.u2);
   return ok;
+}
+
+// Rates of one cell whose relaxation times follow from the ratio eta/s
+// (Sec. III.B), from its particle number N = n gamma and recovered fields:
+//   T = P / n (the ideal-gas relation n = P/T of the initial states),
+//   n_eq = d_G T^3 / pi^2, lambda = n / n_eq, s = 4n - n ln(lambda),
+//   eta = (eta/s) s, and the relation after Eq. (10) solved for tau:
+//   tau_v = 1/2 + kappa eta / (c_s^2 (eps + P) gamma), (eps + P) gamma = sigma / gamma.
+// tau_x (x = f, e, eps, q) with a_x > 0 follow as tau_x - 1/2 = a_x (tau_v - 1/2);
+// tau_q also follows tau_v when tied. A cell with n <= 0 or P <= 0 keeps the
+// member's fixed rates.
+__device__ __forceinline__ Rates local_rates(const Rates& rt, const Visc& v, double N,
+                                             const Macro& m) {
+  constexpr double kPi = 3.141592653589793;
+  const double gam = 1.0 / sqrt(1.0 - m.u2);
+  const double n = N / gam;
+  if (!(v.eta_s > 0.0) || !(n > 0.0) || !(m.P > 0.0)) return rt;
+  const double T = m.P / n;
+  const double n_eq = v.dof * T * T * T / (kPi * kPi);
+  const double s = 4.0 * n - n * log(n / n_eq);
+  const double eta = v.eta_s * s;
+  const double tv = 0.5 + v.kappa * eta / ((1.0 / 3.0) * (m.sigma / gam));
+  Rates r = rt;
+  r.s_v = 1.0 / tv;
+  if (v.q_tied) r.s_q = r.s_v;
+  if (v.a_f > 0.0) r.w_f = 1.0 / (0.5 + v.a_f * (tv - 0.5));
+  if (v.a_e > 0.0) r.s_e = 1.0 / (0.5 + v.a_e * (tv - 0.5));
+  if (v.a_eps > 0.0) r.s_eps = 1.0 / (0.5 + v.a_eps * (tv - 0.5));
+  if (v.a_q > 0.0) r.s_q = 1.0 / (0.5 + v.a_q * (tv - 0.5));
+  return r;
 }
 
 // The 15 non-conserved moments of a population vector.
@@ -363,10 +404,10 @@ __device__ __forceinline__ void collide_g(C (&g)[19], double Mx, double My, doub
 
 // One collision of both distributions in place on the stored deviations.
 // Returns admissibility; sums receives the FP64 Eq. (10) sums of the incoming
-// populations.
-template <typename C>
+// populations. LT: relaxation times of this cell from eta/s (local_rates).
+template <typename C, bool LT = false>
 __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt, const Ref& ref,
-                                        Sums& sums) {
+                                        Sums& sums, const Visc* vis = nullptr) {
   double N, E, Mx, My, Mz, fs, gs;
   cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
   sums.v[0] = N;
@@ -376,8 +417,14 @@ __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt,
   sums.v[4] = Mz;
   Macro mac;
   if (!recover(E, Mx, My, Mz, mac)) return false;
-  collide_f(f, N, fs, mac, rt, ref);
-  collide_g(g, Mx, My, Mz, gs, mac, rt, ref);
+  if constexpr (LT) {
+    const Rates r = local_rates(rt, *vis, N, mac);
+    collide_f(f, N, fs, mac, r, ref);
+    collide_g(g, Mx, My, Mz, gs, mac, r, ref);
+  } else {
+    collide_f(f, N, fs, mac, rt, ref);
+    collide_g(g, Mx, My, Mz, gs, mac, rt, ref);
+  }
   return true;
 }
 

@@ -269,11 +269,14 @@ __device__ __forceinline__ double c7_row(const Macro& m, const C7Fields& fm,
 
 // One collision of both distributions; false (cell untouched) if inadmissible.
 // With CORR, fm / fp are the fields of the y - 1 and y + 1 neighbours and
-// the correction of Eqs. (37)-(38) is applied.
-template <typename C, bool CORR = false>
-__device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt, const Ref& ref,
-                                        Sums& sums, const C7Fields* fm = nullptr,
-                                        const C7Fields* fp = nullptr) {
+// the correction of Eqs. (37)-(38) is applied. LT: relaxation times of this
+// cell from eta/s (local_rates).
+template <typename C, bool CORR = false, bool LT = false>
+__device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt_member,
+                                        const Ref& ref, Sums& sums,
+                                        const C7Fields* fm = nullptr,
+                                        const C7Fields* fp = nullptr,
+                                        const Visc* vis = nullptr) {
   double N, E, Mx, My, fs, gs;
   d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
   sums.v[0] = N;
@@ -283,6 +286,8 @@ __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt, c
   sums.v[4] = 0.0;
   Macro mac;
   if (!recover(E, Mx, My, 0.0, mac)) return false;
+  Rates rt = rt_member;
+  if constexpr (LT) rt = local_rates(rt_member, *vis, N, mac);
   double c7 = 0.0;
   if constexpr (CORR) c7 = d2q9::c7_row(mac, *fm, *fp);
   d2q9::collide_f(f, N, fs, mac, rt, ref);

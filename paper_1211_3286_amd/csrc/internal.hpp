@@ -18,6 +18,7 @@ struct MemberDesc {
   int32_t pad;
   Rates rt;
   Ref ref;
+  Visc vis;  // relaxation times from eta/s (read by the LT kernels only)
 };
 
 // Geometry of a single-lattice launch (the per-step fused kernel).
@@ -27,6 +28,7 @@ struct LatticeGeom {
   int64_t cs;  // plane stride in elements
   Rates rt;
   Ref ref;
+  Visc vis;  // relaxation times from eta/s (read by the LT kernels only)
 };
 
 struct LatticeVariant {
@@ -54,8 +56,9 @@ hipError_t launch_validate(const double* n0, const double* eps0, const double* u
 hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
                        int n_members, const double* n0, const double* eps0, const double* u0,
                        int64_t ncells, hipStream_t s);
-hipError_t launch_step_lattice(int precision, int variant, bool diag, const void* src, void* dst,
-                               const LatticeGeom& g, double* partials,
+// lt: relaxation times of each cell from eta/s (Rates.eta_s > 0).
+hipError_t launch_step_lattice(int precision, int variant, bool diag, bool lt, const void* src,
+                               void* dst, const LatticeGeom& g, double* partials,
                                unsigned long long* bad, hipStream_t s);
 int lattice_partials(int variant, const LatticeGeom& g);  // number of blocks
 // Kernel function pointer and launch shape of the persistent member kernel
@@ -73,7 +76,7 @@ struct MemberLaunch {
   double* partials;
   unsigned long long* bad;
 };
-hipError_t member_kernel(int precision, int variant, const void** func, dim3* block);
+hipError_t member_kernel(int precision, int variant, bool lt, const void** func, dim3* block);
 
 // Segmented persistent step: every member is cut into segments of whole
 // z-planes, one block per segment; a segment waits (per step) for the two
@@ -156,12 +159,13 @@ const char* member_kernel_name(int precision, int variant);
 int d2q9_num_lattice_variants();
 int d2q9_lattice_partials(int variant, const LatticeGeom& g);
 const char* d2q9_lattice_kernel_name(int precision, int variant);
-// corr: apply the correction term of Eqs. (37)-(38) (flows along y).
-hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, bool corr,
+// corr: apply the correction term of Eqs. (37)-(38) (flows along y);
+// lt: relaxation times of each cell from eta/s.
+hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, bool corr, bool lt,
                                     const void* src, void* dst, const LatticeGeom& g,
                                     double* partials, unsigned long long* bad, hipStream_t s);
 int d2q9_num_member_variants();
-hipError_t d2q9_member_kernel(int precision, int variant, bool corr, const void** func,
+hipError_t d2q9_member_kernel(int precision, int variant, bool corr, bool lt, const void** func,
                               dim3* block);
 const char* d2q9_member_kernel_name(int precision, int variant);
 hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,

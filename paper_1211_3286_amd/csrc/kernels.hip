@@ -22,9 +22,10 @@ namespace {
 
 // -------------------------------------------------------------------------
 // Fused step on one lattice: grid (ceil(nx/BX), ceil(ny/BY), ceil(nz/CZ)),
-// block (BX, BY); each thread updates CZ cells along z.
+// block (BX, BY); each thread updates CZ cells along z. LT: relaxation times
+// of each cell from eta/s.
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CZ, bool DIAG>
+template <typename T, int BX, int BY, int CZ, bool DIAG, bool LT>
 __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
         g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
       }
       Sums s;
-      const bool ok = collide<T>(f, g, geo.rt, geo.ref, s);
+      const bool ok = collide<T, LT>(f, g, geo.rt, geo.ref, s, &geo.vis);
       nbad += ok ? 0 : 1;
       if (DIAG)
 #pragma unroll
@@ -79,7 +80,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
 // grid-wide synchronisation exists). Each thread updates CPT cells per sweep,
 // interleaved by NT so every load instruction is coalesced.
 // -------------------------------------------------------------------------
-template <typename T, int NT, int CPT>
+template <typename T, int NT, int CPT, bool LT>
 __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
   const MemberDesc d = a.descs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
             g[q] = ld(src + (int64_t)(19 + q) * a.cs, off[q]);
           }
           Sums s;
-          const bool ok = collide<T>(f, g, d.rt, d.ref, s);
+          const bool ok = collide<T, LT>(f, g, d.rt, d.ref, s, &d.vis);
           nbad += ok ? 0 : 1;
 #pragma unroll
           for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
@@ -511,45 +512,45 @@ int grid_for(int64_t n) {
   return (int)b;
 }
 
-template <typename T, int BX, int BY, int CZ>
+template <typename T, int BX, int BY, int CZ, bool LT>
 hipError_t lat_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                       double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + CZ - 1) / CZ);
   if (diag)
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true>), grid, block, 0, s, (const T*)src,
-                       (T*)dst, g, partials, bad);
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, LT>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, LT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool LT>
 hipError_t lat_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
                         double* partials, unsigned long long* bad, hipStream_t s) {
   switch (v) {
-    case 0: return lat_launch<T, 64, 1, 1>(diag, src, dst, g, partials, bad, s);
-    case 1: return lat_launch<T, 64, 4, 1>(diag, src, dst, g, partials, bad, s);
-    case 2: return lat_launch<T, 128, 2, 1>(diag, src, dst, g, partials, bad, s);
-    case 3: return lat_launch<T, 256, 1, 1>(diag, src, dst, g, partials, bad, s);
-    case 4: return lat_launch<T, 64, 4, 2>(diag, src, dst, g, partials, bad, s);
-    case 5: return lat_launch<T, 256, 1, 2>(diag, src, dst, g, partials, bad, s);
-    case 6: return lat_launch<T, 128, 2, 4>(diag, src, dst, g, partials, bad, s);
-    case 7: return lat_launch<T, 256, 1, 4>(diag, src, dst, g, partials, bad, s);
+    case 0: return lat_launch<T, 64, 1, 1, LT>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat_launch<T, 64, 4, 1, LT>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat_launch<T, 128, 2, 1, LT>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat_launch<T, 256, 1, 1, LT>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat_launch<T, 64, 4, 2, LT>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat_launch<T, 256, 1, 2, LT>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat_launch<T, 128, 2, 4, LT>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat_launch<T, 256, 1, 4, LT>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T>
+template <typename T, bool LT>
 const void* mem_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_step_members<T, 256, 1>;
-    case 1: return (const void*)&k_step_members<T, 512, 1>;
-    case 2: return (const void*)&k_step_members<T, 1024, 1>;
-    case 3: return (const void*)&k_step_members<T, 256, 2>;
-    case 4: return (const void*)&k_step_members<T, 512, 2>;
-    case 5: return (const void*)&k_step_members<T, 1024, 2>;
+    case 0: return (const void*)&k_step_members<T, 256, 1, LT>;
+    case 1: return (const void*)&k_step_members<T, 512, 1, LT>;
+    case 2: return (const void*)&k_step_members<T, 1024, 1, LT>;
+    case 3: return (const void*)&k_step_members<T, 256, 2, LT>;
+    case 4: return (const void*)&k_step_members<T, 512, 2, LT>;
+    case 5: return (const void*)&k_step_members<T, 1024, 2, LT>;
   }
   return nullptr;
 }
@@ -662,16 +663,22 @@ hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc*
   return hipGetLastError();
 }
 
-hipError_t launch_step_lattice(int precision, int v, bool diag, const void* src, void* dst,
-                               const LatticeGeom& g, double* partials,
+hipError_t launch_step_lattice(int precision, int v, bool diag, bool lt, const void* src,
+                               void* dst, const LatticeGeom& g, double* partials,
                                unsigned long long* bad, hipStream_t s) {
-  if (precision) return lat_dispatch<float>(v, diag, src, dst, g, partials, bad, s);
-  return lat_dispatch<double>(v, diag, src, dst, g, partials, bad, s);
+  if (precision)
+    return lt ? lat_dispatch<float, true>(v, diag, src, dst, g, partials, bad, s)
+              : lat_dispatch<float, false>(v, diag, src, dst, g, partials, bad, s);
+  return lt ? lat_dispatch<double, true>(v, diag, src, dst, g, partials, bad, s)
+            : lat_dispatch<double, false>(v, diag, src, dst, g, partials, bad, s);
 }
 
-hipError_t member_kernel(int precision, int v, const void** func, dim3* block) {
+hipError_t member_kernel(int precision, int v, bool lt, const void** func, dim3* block) {
   if (v < 0 || v >= kNumMem) return hipErrorInvalidValue;
-  *func = precision ? mem_func<float>(v) : mem_func<double>(v);
+  if (lt)
+    *func = precision ? mem_func<float, true>(v) : mem_func<double, true>(v);
+  else
+    *func = precision ? mem_func<float, false>(v) : mem_func<double, false>(v);
   *block = dim3(kMem[v].nt, 1, 1);
   return hipSuccess;
 }
@@ -680,7 +687,7 @@ hipError_t launch_step_members(int precision, int v, int n_members, const Member
                                hipStream_t s) {
   const void* f;
   dim3 block;
-  hipError_t e = member_kernel(precision, v, &f, &block);
+  hipError_t e = member_kernel(precision, v, false, &f, &block);
   if (e != hipSuccess) return e;
   void* args[] = {const_cast<MemberLaunch*>(&a)};
   return hipLaunchKernel(f, dim3(n_members), block, args, 0, s);

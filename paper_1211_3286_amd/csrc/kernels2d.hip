@@ -36,7 +36,7 @@ __device__ __forceinline__ void c7_neighbours(const T* __restrict__ src, int64_t
 // correction of Eqs. (37)-(38) (each cell recovers its two y-neighbours from
 // their pulled populations: 18 more loads, mostly L2 hits).
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CY, bool DIAG, bool CORR>
+template <typename T, int BX, int BY, int CY, bool DIAG, bool CORR, bool LT>
 __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -63,7 +63,8 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
         g[a] = ld(src + (int64_t)(9 + a) * geo.cs, off[a]);
       }
       Sums s;
-      const bool ok = d2q9::collide<T, CORR>(f, g, geo.rt, geo.ref, s, &fm, &fp);
+      const bool ok =
+          d2q9::collide<T, CORR, LT>(f, g, geo.rt, geo.ref, s, &fm, &fp, &geo.vis);
       nbad += ok ? 0 : 1;
       if (DIAG)
 #pragma unroll
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
 // Persistent step over a batch of D2Q9 members: one block per member, all
 // nsteps in the launch with a block barrier between steps.
 // -------------------------------------------------------------------------
-template <typename T, int NT, int CPT, bool CORR>
+template <typename T, int NT, int CPT, bool CORR, bool LT>
 __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
   const MemberDesc d = a.descs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -123,7 +124,8 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
             g[q] = ld(src + (int64_t)(9 + q) * a.cs, off[q]);
           }
           Sums s;
-          const bool ok = d2q9::collide<T, CORR>(f, g, d.rt, d.ref, s, &fm, &fp);
+          const bool ok =
+              d2q9::collide<T, CORR, LT>(f, g, d.rt, d.ref, s, &fm, &fp, &d.vis);
           nbad += ok ? 0 : 1;
 #pragma unroll
           for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
@@ -249,44 +251,44 @@ int grid2_for(int64_t n) {
   return (int)b;
 }
 
-template <typename T, int BX, int BY, int CY, bool CORR>
+template <typename T, int BX, int BY, int CY, bool CORR, bool LT>
 hipError_t lat2_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                        double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY * CY - 1) / (BY * CY), 1);
   if (diag)
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR, LT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR, LT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   return hipGetLastError();
 }
 
-template <typename T, bool CORR>
+template <typename T, bool CORR, bool LT>
 hipError_t lat2_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
                          double* partials, unsigned long long* bad, hipStream_t s) {
   switch (v) {
-    case 0: return lat2_launch<T, 64, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
-    case 1: return lat2_launch<T, 128, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
-    case 2: return lat2_launch<T, 256, 1, 1, CORR>(diag, src, dst, g, partials, bad, s);
-    case 3: return lat2_launch<T, 64, 4, 1, CORR>(diag, src, dst, g, partials, bad, s);
-    case 4: return lat2_launch<T, 128, 2, 1, CORR>(diag, src, dst, g, partials, bad, s);
-    case 5: return lat2_launch<T, 256, 1, 2, CORR>(diag, src, dst, g, partials, bad, s);
-    case 6: return lat2_launch<T, 256, 1, 4, CORR>(diag, src, dst, g, partials, bad, s);
-    case 7: return lat2_launch<T, 128, 2, 4, CORR>(diag, src, dst, g, partials, bad, s);
+    case 0: return lat2_launch<T, 64, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat2_launch<T, 128, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat2_launch<T, 256, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat2_launch<T, 64, 4, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat2_launch<T, 128, 2, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat2_launch<T, 256, 1, 2, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat2_launch<T, 256, 1, 4, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat2_launch<T, 128, 2, 4, CORR, LT>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T, bool CORR>
+template <typename T, bool CORR, bool LT>
 const void* mem2_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR>;
-    case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR>;
-    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR>;
-    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR>;
-    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR>;
+    case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR, LT>;
+    case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR, LT>;
+    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR, LT>;
+    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR, LT>;
+    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR, LT>;
   }
   return nullptr;
 }
@@ -314,24 +316,36 @@ const char* d2q9_lattice_kernel_name(int precision, int v) {
   return precision ? n32[v] : n64[v];
 }
 
-hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, bool corr, const void* src,
-                                    void* dst, const LatticeGeom& g, double* partials,
-                                    unsigned long long* bad, hipStream_t s) {
-  if (precision)
-    return corr ? lat2_dispatch<float, true>(v, diag, src, dst, g, partials, bad, s)
-                : lat2_dispatch<float, false>(v, diag, src, dst, g, partials, bad, s);
-  return corr ? lat2_dispatch<double, true>(v, diag, src, dst, g, partials, bad, s)
-              : lat2_dispatch<double, false>(v, diag, src, dst, g, partials, bad, s);
+template <typename T>
+hipError_t lat2_modes(int v, bool diag, bool corr, bool lt, const void* src, void* dst,
+                      const LatticeGeom& g, double* partials, unsigned long long* bad,
+                      hipStream_t s) {
+  if (corr)
+    return lt ? lat2_dispatch<T, true, true>(v, diag, src, dst, g, partials, bad, s)
+              : lat2_dispatch<T, true, false>(v, diag, src, dst, g, partials, bad, s);
+  return lt ? lat2_dispatch<T, false, true>(v, diag, src, dst, g, partials, bad, s)
+            : lat2_dispatch<T, false, false>(v, diag, src, dst, g, partials, bad, s);
+}
+
+hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, bool corr, bool lt,
+                                    const void* src, void* dst, const LatticeGeom& g,
+                                    double* partials, unsigned long long* bad, hipStream_t s) {
+  if (precision) return lat2_modes<float>(v, diag, corr, lt, src, dst, g, partials, bad, s);
+  return lat2_modes<double>(v, diag, corr, lt, src, dst, g, partials, bad, s);
 }
 
 int d2q9_num_member_variants() { return kNumMem2; }
 
-hipError_t d2q9_member_kernel(int precision, int v, bool corr, const void** func, dim3* block) {
+template <typename T>
+const void* mem2_modes(int v, bool corr, bool lt) {
+  if (corr) return lt ? mem2_func<T, true, true>(v) : mem2_func<T, true, false>(v);
+  return lt ? mem2_func<T, false, true>(v) : mem2_func<T, false, false>(v);
+}
+
+hipError_t d2q9_member_kernel(int precision, int v, bool corr, bool lt, const void** func,
+                              dim3* block) {
   if (v < 0 || v >= kNumMem2) return hipErrorInvalidValue;
-  if (corr)
-    *func = precision ? mem2_func<float, true>(v) : mem2_func<double, true>(v);
-  else
-    *func = precision ? mem2_func<float, false>(v) : mem2_func<double, false>(v);
+  *func = precision ? mem2_modes<float>(v, corr, lt) : mem2_modes<double>(v, corr, lt);
   *block = dim3(kMem2[v].nt, 1, 1);
   return hipSuccess;
 }

@@ -23,6 +23,7 @@ problem class the model was built for):
 ``shear_vortex``   2D periodic shear wave + Taylor-Green vortex (adjoint).
 ``blast``          3D spherical blast with an outward velocity shell.
 ``qgp_tube_2d``    the 4 x 800 D2Q9 shock tube of Sec. V.B, Cases A-D.
+``qgp_tube_3d``    the 1 x 1 x 800 D3Q19 shock tube of Sec. III.B at given eta/s.
 """
 
 from __future__ import annotations
@@ -52,6 +53,15 @@ class Params:
     tau_q: float = 0.0  # <= 0: ghost moments relax with tau_v
     lattice: str = "d3q19"  # or "d2q9" (nx x ny x 1, velocities in the x-y plane)
     correction: int = 0  # D2Q9: 1 adds the C_7 term of Eqs. (37)-(38) (flow along y)
+    # Relaxation times from eta/s per cell (Sec. III.B) when eta_s > 0: tau_v from
+    # the local state, scaled by kappa; tau_x - 1/2 = a_x (tau_v - 1/2) where a_x > 0.
+    eta_s: float = 0.0
+    kappa: float = 1.0
+    dof: float = 16.0  # degeneracy d_G of n_eq = d_G T^3 / pi^2 (gluons)
+    a_f: float = 0.0
+    a_e: float = 0.0
+    a_eps: float = 0.0
+    a_q: float = 0.0
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -301,9 +311,22 @@ def case_taus(case: str, tau_v: float, a: float) -> Dict[str, float]:
     return t
 
 
+def case_ratios(case: str, a: float) -> Dict[str, float]:
+    """The Cases of Sec. V.B for relaxation times set per cell from eta/s:
+    tau_x - 1/2 = a_x (tau_v - 1/2) with a_x = a for the reduced ones, 1 else."""
+    r = {"a_e": 1.0, "a_eps": 1.0, "a_q": 1.0}
+    reduced = {"A": (), "B": ("a_q",), "C": ("a_e",), "D": ("a_e", "a_eps")}
+    if case not in reduced:
+        raise ValueError(f"unknown case {case!r}")
+    for k in reduced[case]:
+        r[k] = a
+    return r
+
+
 def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
                 tau_f: float = 0.6, nx: int = 4, length: int = 800, moderate: bool = False,
-                width: float = 1.0, correction: bool = False) -> Problem:
+                width: float = 1.0, correction: bool = False, eta_s: float = 0.0,
+                kappa: float = 4.0 / 3.0) -> Problem:
     """D2Q9 shock tube of Sec. V.B on nx x length x 1 cells.
 
     x is periodic (nx = 4 cells), the long axis y stands for the paper's z
@@ -313,6 +336,9 @@ def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
     1.557e-8, T_L / T_R = 0.0359 / 0.018). n = P / T, u = 0. Relaxation times
     from ``case_taus``; tau_v = 100 stands for the paper's "about 100".
     ``correction`` adds the C_7 term of Eqs. (37)-(38) (the corrected runs).
+    ``eta_s`` > 0: relaxation times per cell from eta/s (scaled by ``kappa``,
+    4/3 for this D2Q9 model), with the case's ratios; tau_v then only serves
+    as the fallback for cells without a temperature.
     """
     st = QGP_MODERATE if moderate else QGP_WEAK
     y = np.arange(length, dtype=np.float64)
@@ -323,12 +349,38 @@ def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
     t = case_taus(case, tau_v, a)
     prm = Params(nx, length, 1, (PERIODIC, ZERO_GRADIENT, PERIODIC), tau_f, t["tau_v"],
                  t["tau_e"], t["tau_eps"], t["tau_q"], "d2q9", int(bool(correction)))
+    if eta_s > 0.0:
+        prm.eta_s, prm.kappa = eta_s, kappa
+        for k, v in case_ratios(case, a).items():
+            setattr(prm, k, v)
     ones = np.ones((1, 1, nx))
     return Problem(prm, (n[None, :, None] * ones).copy(), (3.0 * P[None, :, None] * ones).copy(),
                    np.zeros((3,) + shape),
                    name=f"qgp_tube_2d_{nx}x{length}_case{case}" + ("_moderate" if moderate else "")
-                   + ("_c7" if correction else ""),
+                   + ("_c7" if correction else "") + (f"_eta_s{eta_s}" if eta_s > 0 else ""),
                    meta={"case": case, "a": a})
+
+
+def qgp_tube_3d(eta_s: float = 0.1, tau_f: float | str = "tau_g", length: int = 800,
+                width: float = 1.0, kappa: float = 1.0) -> Problem:
+    """D3Q19 shock tube of Sec. III.B on 1 x 1 x length cells, relaxation
+    times per cell from eta/s (all g rates tied to tau_v, the BGK limit of the
+    MRT). ``tau_f``: "tau_g" ties tau_f to the local tau_g, a number fixes it
+    (the paper's three choices are tau_g, 1.0 and 0.6)."""
+    st = QGP_WEAK
+    z = np.arange(length, dtype=np.float64)
+    P = _tanh_step(z, length / 2.0, width, st["P_L"], st["P_R"])
+    T = _tanh_step(z, length / 2.0, width, st["T_L"], st["T_R"])
+    n = P / T
+    shape = (length, 1, 1)
+    tg = 1.0  # fixed values: only a fallback for cells without a temperature
+    tied = tau_f == "tau_g"
+    prm = Params(1, 1, length, (PERIODIC, PERIODIC, ZERO_GRADIENT), tg if tied else float(tau_f),
+                 tg, tg, tg, 0.0, eta_s=eta_s, kappa=kappa, a_f=1.0 if tied else 0.0,
+                 a_e=1.0, a_eps=1.0)
+    return Problem(prm, n.reshape(shape).copy(), (3.0 * P).reshape(shape).copy(),
+                   np.zeros((3,) + shape),
+                   name=f"qgp_tube_3d_1x1x{length}_eta_s{eta_s}_tau_f_{tau_f}")
 
 
 def uniform(nx: int, ny: int, nz: int, n: float = 1.0, eps: float = 1.0,
@@ -373,9 +425,8 @@ def window(problem: Problem, center: Tuple[int, int, int], half: int):
             loc.append(c - lo)
             sub_bc.append(ZERO_GRADIENT)
     iz, iy, ix = np.ix_(*idx)
-    sub = Params(len(idx[2]), len(idx[1]), len(idx[0]), (sub_bc[2], sub_bc[1], sub_bc[0]),
-                 prm.tau_f, prm.tau_v, prm.tau_e, prm.tau_eps, prm.tau_q, prm.lattice,
-                 prm.correction)
+    sub = dataclasses.replace(prm, nx=len(idx[2]), ny=len(idx[1]), nz=len(idx[0]),
+                              bc=(sub_bc[2], sub_bc[1], sub_bc[0]))
     u = np.stack([problem.u[c][iz, iy, ix] for c in range(3)])
     return (Problem(sub, problem.n[iz, iy, ix].copy(), problem.eps[iz, iy, ix].copy(), u,
                     name=problem.name + "_window"), tuple(loc))
