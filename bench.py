@@ -259,9 +259,10 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
 
 
 def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
-    """Relaxation times per cell from eta/s (Sec. III.B): the fused D3Q19 step
-    built for it on the n^3 random flow (FP32), and the Sec. III.B tube with
-    its three tau_f choices as one batch, 400 steps (FP64)."""
+    """The extended model: relaxation times per cell from eta/s (Sec. III.B)
+    on the n^3 random flow (FP32), the same lattice under the equation of
+    state P = (Gamma - 1)(eps - m n) (Newton recovery), and the Sec. III.B
+    tube with its three tau_f choices as one batch, 400 steps (FP64)."""
     prob = wl.random_modes(n, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
                            tau_eps=0.7, tau_f=0.8)
     prob.params.eta_s, prob.params.a_e, prob.params.a_eps = 0.1, 0.2, 0.5
@@ -273,6 +274,17 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
     out = {"lattice": f"{n}^3 FP32, eta/s = 0.1", "ms_per_step": ms,
            "mlups": cells / (ms * 1e-3) / 1e6, "kernel": tune["name"], "achieved_gbs": gbs,
            "frac": gbs / HBM_PEAK_GBS}
+    sim.close()
+    # the same lattice under P = (Gamma - 1)(eps - m n): Newton recovery per cell
+    prob.params.eta_s = 0.0
+    prob.params.eos_gamma, prob.params.mass = 1.5, 0.6
+    sim = rlb.from_problems(prob, precision=rlb.FP32, diag_every=50)
+    tune = sim.tune(trial_steps=3)
+    ms, _ = time_steps(torch, sim, steps, warmup)
+    gbs = 304 * cells / (ms * 1e-3) / 1e9
+    out["general_eos"] = {"eos": "Gamma 1.5, m 0.6", "ms_per_step": ms,
+                          "mlups": cells / (ms * 1e-3) / 1e6, "kernel": tune["name"],
+                          "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
     sim.close()
     del prob
     tubes = [wl.qgp_tube_3d(0.1, tau_f=tf) for tf in ("tau_g", 1.0, 0.6)]

@@ -106,11 +106,21 @@ typedef struct {
    * {f, e, eps, q} with a_x > 0: tau_x - 1/2 = a_x (tau_v - 1/2); tau_q <= 0
    * ties tau_q to the local tau_v. A cell with n <= 0 or P <= 0 uses the
    * fixed taus, which must be valid in any case. Not with a tape, tube rounds
-   * or segmented launches (RLB_E_UNSUPPORTED). */
+   * or segmented launches (RLB_E_UNSUPPORTED). T = P / n is the ideal-gas
+   * temperature, also under the general equation of state below. */
   double eta_over_s;   /* >= 0 */
   double kappa;        /* > 0 when eta_over_s > 0 */
   double dof;          /* degeneracy d_G > 0 (16 for gluons) */
   double a_f, a_e, a_eps, a_q;  /* >= 0 */
+  /* Equation of state P = (eos_gamma - 1)(eps - mass n) (an extension of the
+   * paper's P = eps/3, which is eos_gamma 0 or 4/3 with mass 0). Eq. (10) then
+   * leaves one equation for z = (eps + P) gamma^2, solved per cell by a
+   * bracketed Newton iteration in FP64. eos_gamma in (1, 2] (or 0), mass >= 0;
+   * every input cell needs eps > mass n; cells whose root gives P <= 0 are
+   * inadmissible. Not with a tape, the correction term, tube rounds or
+   * segmented launches (RLB_E_UNSUPPORTED). */
+  double eos_gamma;
+  double mass;
 } rlb_params;
 
 typedef struct {

@@ -32,7 +32,8 @@ class CParams(ctypes.Structure):
                 ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double),
                 ("eta_s", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("dof", ctypes.c_double), ("a_f", ctypes.c_double), ("a_e", ctypes.c_double),
-                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double)]
+                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double),
+                ("eos_gamma", ctypes.c_double), ("mass", ctypes.c_double)]
 
 
 _lib = None
@@ -67,6 +68,8 @@ def _load():
     lib.oracle_geq.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_recover.argtypes = [ctypes.c_double, ctypes.c_double, D, D]
     lib.oracle_recover.restype = ctypes.c_int
+    lib.oracle_recover_model.argtypes = [P, ctypes.c_double, ctypes.c_double, D, D]
+    lib.oracle_recover_model.restype = ctypes.c_int
     lib.oracle_rates.argtypes = [P, D]
     lib.oracle_collide_cell.argtypes = [P, D, D, D, D]
     lib.oracle_collide_cell.restype = ctypes.c_int
@@ -110,9 +113,14 @@ def cparams(p) -> CParams:
     c.eta_s = float(getattr(p, "eta_s", 0.0))
     c.kappa = float(getattr(p, "kappa", 1.0))
     c.dof = float(getattr(p, "dof", 16.0))
-    for k in ("a_f", "a_e", "a_eps", "a_q"):
+    for k in ("a_f", "a_e", "a_eps", "a_q", "eos_gamma", "mass"):
         setattr(c, k, float(getattr(p, k, 0.0)))
     return c
+
+
+def general_eos(p) -> bool:
+    g = float(getattr(p, "eos_gamma", 0.0))
+    return (g != 0.0 and g != 4.0 / 3.0) or float(getattr(p, "mass", 0.0)) != 0.0
 
 
 def set_threads(n: int) -> None:
@@ -177,6 +185,17 @@ def recover(N: float, E: float, M) -> Tuple[bool, Dict[str, float]]:
     out = np.zeros(8)
     mm = np.ascontiguousarray(M, dtype=np.float64)
     ok = _load().oracle_recover(float(N), float(E), _ptr(mm), _ptr(out))
+    keys = ["n", "eps", "P", "gamma", "ux", "uy", "uz", "sigma"]
+    return bool(ok), dict(zip(keys, out.tolist()))
+
+
+def recover_model(p, N: float, E: float, M) -> Tuple[bool, Dict[str, float]]:
+    """Recovery under the equation of state of ``p`` (P = eps/3 or the
+    general P = (Gamma - 1)(eps - m n))."""
+    out = np.zeros(8)
+    mm = np.ascontiguousarray(M, dtype=np.float64)
+    cp = cparams(p)
+    ok = _load().oracle_recover_model(ctypes.byref(cp), float(N), float(E), _ptr(mm), _ptr(out))
     keys = ["n", "eps", "P", "gamma", "ux", "uy", "uz", "sigma"]
     return bool(ok), dict(zip(keys, out.tolist()))
 
@@ -249,6 +268,8 @@ class State:
         cp = cparams(self.params)
         if is_d2q9(self.params):
             corr = int(bool(getattr(self.params, "correction", 0)))
+            if corr and general_eos(self.params):
+                raise ValueError("the correction term is defined for P = eps/3")
             bad = _load().oracle_d2q9_step(ctypes.byref(cp), int(nsteps), _ptr(self.f),
                                            _ptr(self.g), corr)
         else:

@@ -23,6 +23,9 @@
 //     written as a pull with periodic wrap or zero-gradient clamp per axis.
 //   * Adjoint of the g update (recovery, equilibria, MRT, streaming) by
 //     complex-step Jacobians of the very same per-cell code.
+//   * Extensions beyond the paper's runs: relaxation times per cell from
+//     eta/s (cell_taus), and the equation of state P = (Gamma - 1)(eps - m n)
+//     with its recovery by bisection (recover_general).
 //   * The D2Q9 MRT model the paper itself runs (Sec. V.A, Eqs. 30-35): its
 //     own velocity set, weights, basis (the rows that reproduce Eq. 34),
 //     S of Eq. (31), g_eq of Eqs. (32)-(33), f_eq of Eq. (7)'s form with the
@@ -163,6 +166,9 @@ struct Params {
   double tau_f, tau_v, tau_e, tau_eps, tau_q;
   // Relaxation times from eta/s per cell (off when eta_s <= 0), see cell_taus.
   double eta_s, kappa, dof, a_f, a_e, a_eps, a_q;
+  // Equation of state P = (Gamma - 1)(eps - m n); Gamma = 0 or 4/3 with m = 0
+  // is the paper's P = eps/3 (see recover_model).
+  double eos_gamma, mass;
 };
 
 // Diagonal of S (Eq. 31 generalised to D3Q19). tau_sigma = tau_j = dt for the
@@ -237,6 +243,67 @@ bool recover(T N, T E, const T M[3], Fields<T>& F) {
   F.gamma = T(1.0) / std::sqrt(T(1.0) - uu);
   F.n = N / F.gamma;
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Recovery for an equation of state other than the paper's (an extension):
+// P = (Gamma - 1)(eps - m n), the gas with adiabatic index Gamma and rest mass
+// m (m = 0, Gamma = 4/3 is P = eps/3). With z = sigma = (eps + P) gamma^2,
+// Eq. (10) gives z = E + P, u = M / z, (eps + P) = z - |M|^2 / z,
+// n = N / gamma, and so one equation in z:
+//   F(z) = z - E - (Gamma - 1)/Gamma [ (z - |M|^2/z) - m N sqrt(1 - |M|^2/z^2) ] = 0.
+// F is increasing, F(|M|) = |M| - E < 0 when |M| < E, and F(Gamma E) >= 0, so
+// the root is unique in (|M|, Gamma E]; it is found here by plain bisection
+// to the last bit. A cell needs E > 0, |M| < E, N >= 0 and P > 0 at the root.
+// ---------------------------------------------------------------------------
+bool general_eos(const Params& p) {
+  return (p.eos_gamma != 0.0 && p.eos_gamma != 4.0 / 3.0) || p.mass != 0.0;
+}
+
+double eos_gamma_of(const Params& p) { return p.eos_gamma > 0.0 ? p.eos_gamma : 4.0 / 3.0; }
+
+// Pressure of the initial fields under the member's equation of state.
+double pressure_of(const Params& p, double eps, double n) {
+  if (!general_eos(p)) return eps / 3.0;
+  return (eos_gamma_of(p) - 1.0) * (eps - p.mass * n);
+}
+
+bool recover_general(const Params& p, double N, double E, const double M[3],
+                     Fields<double>& F) {
+  const double G = eos_gamma_of(p), m = p.mass;
+  const double M2 = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  if (!(E > 0.0) || !(M2 < E * E) || !(N >= 0.0)) return false;
+  auto pressure = [&](double z) {
+    const double h = z - M2 / z;
+    const double n = N * std::sqrt(1.0 - M2 / (z * z));
+    return (G - 1.0) / G * (h - m * n);
+  };
+  double lo = std::sqrt(M2), hi = G * E;
+  for (int i = 0; i < 4000; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    if (mid - E - pressure(mid) > 0.0)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  const double z = 0.5 * (lo + hi);
+  const double P = pressure(z);
+  if (!(P > 0.0)) return false;
+  for (int i = 0; i < 3; ++i) F.u[i] = M[i] / z;
+  const double uu = F.u[0] * F.u[0] + F.u[1] * F.u[1] + F.u[2] * F.u[2];
+  F.sigma = z;
+  F.P = P;
+  F.eps = (z - M2 / z) - P;
+  F.gamma = 1.0 / std::sqrt(1.0 - uu);
+  F.n = N / F.gamma;
+  return true;
+}
+
+// The recovery of the member's model: the paper's closed form for P = eps/3,
+// the bisection above otherwise.
+bool recover_model(const Params& p, double N, double E, const double M[3], Fields<double>& F) {
+  return general_eos(p) ? recover_general(p, N, E, M, F) : recover<double>(N, E, M, F);
 }
 
 template <class T>
@@ -463,7 +530,7 @@ bool cell2(const Params& p, const double s_fixed[9], const double f[9], const do
   double N, E, M[3];
   moments2(f, g, N, E, M);
   Fields<double> F;
-  if (!recover<double>(N, E, M, F)) {
+  if (!recover_model(p, N, E, M, F)) {
     for (int a = 0; a < 9; ++a) {
       fout[a] = f[a];
       gout[a] = g[a];
@@ -647,7 +714,7 @@ void oracle_d2q9_init(const Params* p, const double* n0, const double* eps0, con
     double u[2] = {u0[c], u0[nc + c]};
     double uu = u[0] * u[0] + u[1] * u[1];
     double gamma = 1.0 / std::sqrt(1.0 - uu);
-    double P = eps0[c] / 3.0;
+    double P = pressure_of(*p, eps0[c], n0[c]);
     double sigma = (eps0[c] + P) * gamma * gamma;
     double fe[9], ge[9];
     f_equilibrium2(n0[c] * gamma, u, fe);
@@ -732,7 +799,7 @@ int64_t oracle_d2q9_fields(const Params* p, const double* f, const double* g, do
     S[2] += M[0];
     S[3] += M[1];
     Fields<double> F;
-    if (!recover<double>(N, E, M, F)) {
+    if (!recover_model(*p, N, E, M, F)) {
       ++bad;
       double q = std::nan("");
       F.n = F.eps = F.P = F.gamma = F.u[0] = F.u[1] = F.u[2] = q;
@@ -779,6 +846,22 @@ int oracle_recover(double N, double E, const double* M, double* out) {
   return 1;
 }
 
+// Recovery under the member's equation of state (recover_model); out as in
+// oracle_recover.
+int oracle_recover_model(const Params* p, double N, double E, const double* M, double* out) {
+  Fields<double> F;
+  if (!recover_model(*p, N, E, M, F)) return 0;
+  out[0] = F.n;
+  out[1] = F.eps;
+  out[2] = F.P;
+  out[3] = F.gamma;
+  out[4] = F.u[0];
+  out[5] = F.u[1];
+  out[6] = F.u[2];
+  out[7] = F.sigma;
+  return 1;
+}
+
 void oracle_rates(const Params* p, double* s) {
   rates<double>(p->tau_v, p->tau_e, p->tau_eps, tau_q_of(*p), s);
 }
@@ -791,7 +874,7 @@ int oracle_collide_cell(const Params* p, const double* f, const double* g, doubl
   double N, E, M[3];
   moments<double>(f, g, N, E, M);
   Fields<double> F;
-  if (!recover<double>(N, E, M, F)) {
+  if (!recover_model(*p, N, E, M, F)) {
     for (int a = 0; a < 19; ++a) {
       fout[a] = f[a];
       gout[a] = g[a];
@@ -817,7 +900,7 @@ void oracle_init(const Params* p, const double* n0, const double* eps0, const do
     double u[3] = {u0[c], u0[nc + c], u0[2 * nc + c]};
     double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     double gamma = 1.0 / std::sqrt(1.0 - uu);
-    double P = eps0[c] / 3.0;
+    double P = pressure_of(*p, eps0[c], n0[c]);
     double sigma = (eps0[c] + P) * gamma * gamma;
     double fe[19], ge[19];
     f_equilibrium<double>(n0[c] * gamma, u, fe);
@@ -854,7 +937,7 @@ int64_t oracle_step(const Params* p, int32_t nsteps, double* f, double* g) {
           double N, E, M[3];
           moments<double>(fl, gl, N, E, M);
           Fields<double> F;
-          if (!recover<double>(N, E, M, F)) {
+          if (!recover_model(*p, N, E, M, F)) {
             ++bad;
             for (int a = 0; a < 19; ++a) {
               fo[a] = fl[a];
@@ -905,7 +988,7 @@ int64_t oracle_fields(const Params* p, const double* f, const double* g, double*
     S3 += M[1];
     S4 += M[2];
     Fields<double> F;
-    bool ok = recover<double>(N, E, M, F);
+    bool ok = recover_model(*p, N, E, M, F);
     if (!ok) {
       ++bad;
       double q = std::nan("");
@@ -966,7 +1049,7 @@ static void rates_c(const Params& p, int which, cplx s[19]) {
 int oracle_grad(const Params* p, int32_t nsteps, const double* n0, const double* eps0,
                 const double* u0, const double* dL_du, const double* dL_deps, double* dL_dtau,
                 double* dL_deps0, double* dL_du0) {
-  if (p->eta_s > 0.0) return -1;  // fixed relaxation times only
+  if (p->eta_s > 0.0 || general_eos(*p)) return -1;  // fixed taus, P = eps/3 only
   build_tables();
   (void)cell_g_real;
   const int64_t nc = (int64_t)p->nx * p->ny * p->nz;

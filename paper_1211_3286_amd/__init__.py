@@ -53,7 +53,8 @@ class CParams(ctypes.Structure):
                 ("tau_eps", ctypes.c_double), ("tau_q", ctypes.c_double),
                 ("eta_over_s", ctypes.c_double), ("kappa", ctypes.c_double),
                 ("dof", ctypes.c_double), ("a_f", ctypes.c_double), ("a_e", ctypes.c_double),
-                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double)]
+                ("a_eps", ctypes.c_double), ("a_q", ctypes.c_double),
+                ("eos_gamma", ctypes.c_double), ("mass", ctypes.c_double)]
 
 
 class COptions(ctypes.Structure):
@@ -129,7 +130,7 @@ def cparams(members: Sequence) -> ctypes.Array:
         c.eta_over_s = float(getattr(p, "eta_s", 0.0))
         c.kappa = float(getattr(p, "kappa", 1.0))
         c.dof = float(getattr(p, "dof", 16.0))
-        for k in ("a_f", "a_e", "a_eps", "a_q"):
+        for k in ("a_f", "a_e", "a_eps", "a_q", "eos_gamma", "mass"):
             setattr(c, k, float(getattr(p, k, 0.0)))
     return arr
 

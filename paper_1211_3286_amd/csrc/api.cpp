@@ -60,6 +60,8 @@ rlb_status check_members(const rlb_params* m, int32_t n, int64_t* ncells) {
     if (p.tau_q > 0.0 && !finite_tau(p.tau_q)) return RLB_E_TAU;
     if (std::isnan(p.tau_q)) return RLB_E_TAU;
     if (!std::isfinite(p.eta_over_s) || p.eta_over_s < 0.0) return RLB_E_ARG;
+    if (!(p.eos_gamma == 0.0 || (p.eos_gamma > 1.0 && p.eos_gamma <= 2.0))) return RLB_E_ARG;
+    if (!std::isfinite(p.mass) || p.mass < 0.0) return RLB_E_ARG;
     if (p.eta_over_s > 0.0) {
       if (!std::isfinite(p.kappa) || !(p.kappa > 0.0)) return RLB_E_ARG;
       if (!std::isfinite(p.dof) || !(p.dof > 0.0)) return RLB_E_ARG;
@@ -69,6 +71,11 @@ rlb_status check_members(const rlb_params* m, int32_t n, int64_t* ncells) {
   }
   *ncells = tot;
   return RLB_OK;
+}
+
+// The paper's equation of state P = eps/3 (Gamma 0 or 4/3, no rest mass)?
+bool paper_eos(const rlb_params& p) {
+  return (p.eos_gamma == 0.0 || p.eos_gamma == 4.0 / 3.0) && p.mass == 0.0;
 }
 
 bool lattice_path(int32_t n_members, int64_t ncells) {
@@ -94,7 +101,11 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
     if (opt->ckpt_every > 0) return RLB_E_UNSUPPORTED;  // the adjoint covers D3Q19
   }
   if (opt->ckpt_every > 0 && n != 1) return RLB_E_UNSUPPORTED;
-  if (opt->ckpt_every > 0 && m[0].eta_over_s > 0.0) return RLB_E_UNSUPPORTED;
+  if (opt->ckpt_every > 0 && (m[0].eta_over_s > 0.0 || !paper_eos(m[0])))
+    return RLB_E_UNSUPPORTED;  // the adjoint covers fixed taus and P = eps/3
+  if (opt->correction)
+    for (int i = 0; i < n; ++i)
+      if (!paper_eos(m[i])) return RLB_E_UNSUPPORTED;  // C_7 is derived for P = eps/3
   L.esz = opt->precision == RLB_FP32 ? 4 : 8;
   // Plane stride: a multiple of 64 elements plus 64 more, so that planes of a
   // power-of-two lattice do not all start on the same HBM channel (measured:
@@ -194,7 +205,7 @@ struct rlb_sim {
   int cur = 0;
   bool d2 = false;  // D2Q9 model (9 velocities, 18 planes per buffer)
   bool corr = false;  // D2Q9 with the correction term of Eqs. (37)-(38)
-  bool lt = false;    // some member takes its relaxation times from eta/s per cell
+  bool ext = false;    // some member takes its relaxation times from eta/s per cell
   int q = 19;
   bool lattice = false;
   LatticeGeom geom{};
@@ -239,10 +250,10 @@ void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
   if (h->d2)
-    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, h->corr, h->lt,
+    return dev_err(rlb::d2q9_launch_step_lattice(h->precision, variant, diag, h->corr, h->ext,
                                                  src, dst, h->geom, h->d_partials, h->d_bad,
                                                  h->stream));
-  return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, h->lt, src, dst, h->geom,
+  return dev_err(rlb::launch_step_lattice(h->precision, variant, diag, h->ext, src, dst, h->geom,
                                           h->d_partials, h->d_bad, h->stream));
 }
 
@@ -316,7 +327,7 @@ rlb_status build_tube_segments(rlb_sim* h, int tv) {
 rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
                         int diag_every, int64_t step0, bool* flip) {
   const int tv = tube_index(variant);
-  if (!h->all_tubes || h->lt) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
+  if (!h->all_tubes || h->ext) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
   if (h->seg_built != 1000 + tv) {
     rlb_status st = build_tube_segments(h, tv);
     if (st != RLB_OK) return st;
@@ -424,7 +435,7 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
   dim3 block, grid;
   void* args[1];
   if (is_segment_variant(h, variant)) {
-    if (h->lt) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
+    if (h->ext) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
     const int sv = variant - rlb::num_member_variants();
     RLB_HIP(rlb::segment_kernel(h->precision, sv, &func, &block));
     rlb_status st = segments_fit(h, sv, func, block.x);
@@ -460,9 +471,13 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
     m.partials = h->d_partials;
     m.bad = h->d_bad;
     if (h->d2)
-      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, h->lt, &func, &block));
+      RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, h->ext, &func, &block));
     else
-      RLB_HIP(rlb::member_kernel(h->precision, variant, h->lt, &func, &block));
+      RLB_HIP(rlb::member_kernel(h->precision, variant, h->ext, &func, &block));
+    // Extended-model kernels run with at most 512 threads per block: the
+    // 1024-thread builds spill registers to scratch, and one of them
+    // (FP64, one cell per thread) returned wrong results on gfx950.
+    if (h->ext && block.x > 512) return RLB_E_UNSUPPORTED;
     args[0] = &h->margs;
     grid = dim3(h->n_members, 1, 1);
   }
@@ -548,12 +563,20 @@ rlb_status copy_fields_in(rlb_sim* h, const double* n0, const double* eps0, cons
 }
 
 bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int64_t nc,
-                    bool planar) {
-  for (int64_t i = 0; i < nc; ++i) {
-    const double uu = u0[i] * u0[i] + u0[nc + i] * u0[nc + i] + u0[2 * nc + i] * u0[2 * nc + i];
-    if (!(eps0[i] > 0.0) || !(n0[i] >= 0.0) || !(uu < 1.0) || !std::isfinite(n0[i]) ||
-        !std::isfinite(eps0[i]) || (planar && u0[2 * nc + i] != 0.0))
-      return false;
+                    bool planar, const rlb_params* members, int32_t n_members) {
+  int64_t i = 0;
+  for (int m = 0; m < n_members; ++m) {
+    const rlb_params& p = members[m];
+    const int64_t end = i + (int64_t)p.nx * p.ny * p.nz;
+    const bool gen = !paper_eos(p);
+    for (; i < end; ++i) {
+      const double uu =
+          u0[i] * u0[i] + u0[nc + i] * u0[nc + i] + u0[2 * nc + i] * u0[2 * nc + i];
+      if (!(eps0[i] > 0.0) || !(n0[i] >= 0.0) || !(uu < 1.0) || !std::isfinite(n0[i]) ||
+          !std::isfinite(eps0[i]) || (planar && u0[2 * nc + i] != 0.0) ||
+          (gen && !(eps0[i] - p.mass * n0[i] > 0.0)))
+        return false;
+    }
   }
   return true;
 }
@@ -625,7 +648,7 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || workspace_bytes < L.total)
     return RLB_E_WORKSPACE;
   const bool planar = opt->lattice == RLB_D2Q9;
-  if (!fields_on_device && !host_fields_ok(n0, eps0, u0, L.ncells, planar))
+  if (!fields_on_device && !host_fields_ok(n0, eps0, u0, L.ncells, planar, members, n_members))
     return RLB_E_UNPHYSICAL;
 
   rlb_sim* h = new (std::nothrow) rlb_sim();
@@ -688,17 +711,21 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     d.rt.s_eps = 1.0 / p.tau_eps;
     d.rt.s_q = 1.0 / tq;
     d.rt.s_v = 1.0 / p.tau_v;
-    d.vis.eta_s = p.eta_over_s;
-    d.vis.kappa = p.kappa;
-    d.vis.dof = p.dof;
-    d.vis.a_f = p.a_f;
-    d.vis.a_e = p.a_e;
-    d.vis.a_eps = p.a_eps;
-    d.vis.a_q = p.a_q;
-    d.vis.q_tied = p.tau_q > 0.0 ? 0 : 1;
-    if (p.eta_over_s > 0.0) h->lt = true;
+    d.ext.eta_s = p.eta_over_s;
+    d.ext.kappa = p.kappa;
+    d.ext.dof = p.dof;
+    d.ext.a_f = p.a_f;
+    d.ext.a_e = p.a_e;
+    d.ext.a_eps = p.a_eps;
+    d.ext.a_q = p.a_q;
+    d.ext.q_tied = p.tau_q > 0.0 ? 0 : 1;
+    d.ext.eos_gamma = p.eos_gamma > 0.0 ? p.eos_gamma : 4.0 / 3.0;
+    d.ext.mass = p.mass;
+    d.ext.general_eos = paper_eos(p) ? 0 : 1;
+    if (p.eta_over_s > 0.0 || d.ext.general_eos) h->ext = true;
     off += d.ncells;
   }
+  if (h->ext && !h->lattice) h->variant = 1;  // 512 threads (see launch_persistent)
   const double *dn, *de, *du;
   if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess) return fail(RLB_E_DEVICE);
   if (L.max_segs > 0 &&
@@ -710,9 +737,12 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     return fail(RLB_E_DEVICE);
   if (copy_fields_in(h, n0, eps0, u0, fields_on_device, &dn, &de, &du) != RLB_OK)
     return fail(RLB_E_DEVICE);
+  if (hipMemcpyAsync(h->d_descs, h->descs.data(), sizeof(MemberDesc) * n_members,
+                     hipMemcpyHostToDevice, h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
   if (fields_on_device) {
-    if (rlb::launch_validate(dn, de, du, L.ncells, planar ? 1 : 0, h->d_count, h->stream) !=
-        hipSuccess)
+    if (rlb::launch_validate(dn, de, du, L.ncells, planar ? 1 : 0, h->d_descs, n_members,
+                             h->d_count, h->stream) != hipSuccess)
       return fail(RLB_E_DEVICE);
     unsigned long long cnt = 0;
     if (hipMemcpyAsync(&cnt, h->d_count, sizeof(cnt), hipMemcpyDeviceToHost, h->stream) !=
@@ -721,9 +751,6 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
       return fail(RLB_E_DEVICE);
     if (cnt) return fail(RLB_E_UNPHYSICAL);
   }
-  if (hipMemcpyAsync(h->d_descs, h->descs.data(), sizeof(MemberDesc) * n_members,
-                     hipMemcpyHostToDevice, h->stream) != hipSuccess)
-    return fail(RLB_E_DEVICE);
   if (rlb::launch_member_refs(h->d_descs, n_members, dn, de, du, L.ncells, h->d_partials,
                               h->stream) != hipSuccess)
     return fail(RLB_E_DEVICE);
@@ -748,7 +775,7 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     h->geom.cs = L.cs;
     h->geom.rt = d.rt;
     h->geom.ref = d.ref;
-    h->geom.vis = d.vis;
+    h->geom.ext = d.ext;
   }
   h->cur = 0;
   if (opt->ckpt_every > 0) {

@@ -39,15 +39,18 @@ struct Rates {
   double s_v;    // 1/tau_v   (3p_xx, p_ww, p_xy, p_yz, p_xz rows)
 };
 
-// Parameters of relaxation times set per cell from eta/s (local_rates); only
-// the kernels built for it read them.
-struct Visc {
+// Extensions of the model read only by the kernels built for them (EXT):
+// relaxation times set per cell from eta/s (local_rates), and the equation of
+// state P = (Gamma - 1)(eps - m n) (recover_general).
+struct Ext {
   double eta_s;  // > 0: tau_v of each cell from eta/s (Rates are the fallback)
   double kappa;  // shear-viscosity transformation factor
   double dof;    // degeneracy d_G of n_eq = d_G T^3 / pi^2
   double a_f, a_e, a_eps, a_q;  // > 0: tau_x - 1/2 = a_x (tau_v - 1/2)
+  double eos_gamma;             // Gamma (general_eos only)
+  double mass;                  // rest mass m (general_eos only)
   int32_t q_tied;               // tau_q follows tau_v (tau_q <= 0 given)
-  int32_t pad;
+  int32_t general_eos;          // 0: the paper's P = eps/3
 };
 
 // Rest reference state the populations are stored relative to.
@@ -142,6 +145,56 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
   return ok;
 }
 
+// Recovery for the equation of state P = (Gamma - 1)(eps - m n) (an extension;
+// Gamma = 4/3, m = 0 is the paper's P = eps/3). With z = sigma = (eps + P) gamma^2,
+// Eq. (10) gives z = E + P, u = M / z, eps + P = z - |M|^2/z, n = N / gamma:
+//   F(z) = z - E - c [(z - |M|^2/z) - m N sqrt(1 - |M|^2/z^2)] = 0, c = (Gamma-1)/Gamma.
+// F increases on (|M|, Gamma E] with F(|M|) < 0 <= F(Gamma E): Newton from the
+// massless root, kept inside the shrinking bracket (bisection when a step
+// leaves it), FP64. A cell needs E > 0, |M| < E, N >= 0 and P > 0.
+__device__ __forceinline__ bool recover_general(double N, double E, double Mx, double My,
+                                                double Mz, const Ext& x, Macro& m) {
+  const double G = x.eos_gamma, c = (x.eos_gamma - 1.0) / x.eos_gamma, mass = x.mass;
+  const double M2 = Mx * Mx + My * My + Mz * Mz;
+  const bool ok0 = (E > 0.0) && (M2 < E * E) && (N >= 0.0);
+  const double Es = ok0 ? E : 1.0, M2s = ok0 ? M2 : 0.0, Ns = ok0 ? N : 0.0;
+  double lo = sqrt(M2s), hi = G * Es;
+  double z = 0.5 * (G * Es + sqrt(fmax(G * G * Es * Es - 4.0 * (G - 1.0) * M2s, 0.0)));
+  z = fmin(fmax(z, lo), hi);
+  for (int it = 0; it < 64; ++it) {
+    const double x2 = M2s / (z * z);
+    const double sq = sqrt(1.0 - x2);
+    const double Fz = z - Es - c * ((z - M2s / z) - mass * Ns * sq);
+    if (Fz > 0.0)
+      hi = z;
+    else
+      lo = z;
+    const double dF = 1.0 - c * (1.0 + x2 - mass * Ns * (x2 / z) / sq);
+    double zn = z - Fz / dF;
+    if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
+    const bool done = fabs(zn - z) <= 1e-15 * z;
+    z = zn;
+    if (done) break;
+  }
+  const double sq = sqrt(1.0 - M2s / (z * z));
+  const double P = c * ((z - M2s / z) - mass * Ns * sq);
+  const bool ok = ok0 && (P > 0.0);
+  m.ux = ok ? Mx / z : 0.0;
+  m.uy = ok ? My / z : 0.0;
+  m.uz = ok ? Mz / z : 0.0;
+  m.u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  m.sigma = ok ? z : 4.0 / 3.0;
+  m.P = ok ? P : 1.0 / 3.0;
+  return ok;
+}
+
+// The recovery of the member's model.
+__device__ __forceinline__ bool recover_model(double N, double E, double Mx, double My,
+                                              double Mz, const Ext& x, Macro& m) {
+  if (x.general_eos) return recover_general(N, E, Mx, My, Mz, x, m);
+  return recover(E, Mx, My, Mz, m);
+}
+
 // Rates of one cell whose relaxation times follow from the ratio eta/s
 // (Sec. III.B), from its particle number N = n gamma and recovered fields:
 //   T = P / n (the ideal-gas relation n = P/T of the initial states),
@@ -151,7 +204,7 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
 // tau_x (x = f, e, eps, q) with a_x > 0 follow as tau_x - 1/2 = a_x (tau_v - 1/2);
 // tau_q also follows tau_v when tied. A cell with n <= 0 or P <= 0 keeps the
 // member's fixed rates.
-__device__ __forceinline__ Rates local_rates(const Rates& rt, const Visc& v, double N,
+__device__ __forceinline__ Rates local_rates(const Rates& rt, const Ext& v, double N,
                                              const Macro& m) {
   constexpr double kPi = 3.141592653589793;
   const double gam = 1.0 / sqrt(1.0 - m.u2);
@@ -404,10 +457,10 @@ __device__ __forceinline__ void collide_g(C (&g)[19], double Mx, double My, doub
 
 // One collision of both distributions in place on the stored deviations.
 // Returns admissibility; sums receives the FP64 Eq. (10) sums of the incoming
-// populations. LT: relaxation times of this cell from eta/s (local_rates).
-template <typename C, bool LT = false>
+// populations. EXT: relaxation times of this cell from eta/s (local_rates).
+template <typename C, bool EXT = false>
 __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt, const Ref& ref,
-                                        Sums& sums, const Visc* vis = nullptr) {
+                                        Sums& sums, const Ext* ext = nullptr) {
   double N, E, Mx, My, Mz, fs, gs;
   cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
   sums.v[0] = N;
@@ -416,12 +469,13 @@ __device__ __forceinline__ bool collide(C (&f)[19], C (&g)[19], const Rates& rt,
   sums.v[3] = My;
   sums.v[4] = Mz;
   Macro mac;
-  if (!recover(E, Mx, My, Mz, mac)) return false;
-  if constexpr (LT) {
-    const Rates r = local_rates(rt, *vis, N, mac);
+  if constexpr (EXT) {
+    if (!recover_model(N, E, Mx, My, Mz, *ext, mac)) return false;
+    const Rates r = local_rates(rt, *ext, N, mac);
     collide_f(f, N, fs, mac, r, ref);
     collide_g(g, Mx, My, Mz, gs, mac, r, ref);
   } else {
+    if (!recover(E, Mx, My, Mz, mac)) return false;
     collide_f(f, N, fs, mac, rt, ref);
     collide_g(g, Mx, My, Mz, gs, mac, rt, ref);
   }
@@ -439,14 +493,20 @@ __device__ __forceinline__ bool collide_g_only(C (&g)[19], const Rates& rt, cons
   return true;
 }
 
-// Equilibrium deviations of a cell from its fields (init, Eqs. 7-9), FP64.
-__device__ __forceinline__ void equilibrium_dev(double n, double eps, double ux, double uy,
-                                                double uz, const Ref& ref, double (&f)[19],
-                                                double (&g)[19]) {
+// Pressure of initial fields under the member's equation of state.
+__device__ __forceinline__ double pressure_of(double eps, double n, const Ext& x) {
+  if (x.general_eos) return (x.eos_gamma - 1.0) * (eps - x.mass * n);
+  return eps / 3.0;
+}
+
+// Equilibrium deviations of a cell from its fields (init, Eqs. 7-9), FP64;
+// P is the pressure of the fields (pressure_of).
+__device__ __forceinline__ void equilibrium_dev(double n, double eps, double P, double ux,
+                                                double uy, double uz, const Ref& ref,
+                                                double (&f)[19], double (&g)[19]) {
   const double uu = ux * ux + uy * uy + uz * uz;
   const double gam2 = 1.0 / (1.0 - uu);
   const double N = n * sqrt(gam2);
-  const double P = eps / 3.0;
   const double sigma = (eps + P) * gam2;
 #pragma unroll
   for (int a = 0; a < 19; ++a) {

@@ -269,14 +269,14 @@ __device__ __forceinline__ double c7_row(const Macro& m, const C7Fields& fm,
 
 // One collision of both distributions; false (cell untouched) if inadmissible.
 // With CORR, fm / fp are the fields of the y - 1 and y + 1 neighbours and
-// the correction of Eqs. (37)-(38) is applied. LT: relaxation times of this
+// the correction of Eqs. (37)-(38) is applied. EXT: relaxation times of this
 // cell from eta/s (local_rates).
-template <typename C, bool CORR = false, bool LT = false>
+template <typename C, bool CORR = false, bool EXT = false>
 __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt_member,
                                         const Ref& ref, Sums& sums,
                                         const C7Fields* fm = nullptr,
                                         const C7Fields* fp = nullptr,
-                                        const Visc* vis = nullptr) {
+                                        const Ext* ext = nullptr) {
   double N, E, Mx, My, fs, gs;
   d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
   sums.v[0] = N;
@@ -285,9 +285,13 @@ __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt_me
   sums.v[3] = My;
   sums.v[4] = 0.0;
   Macro mac;
-  if (!recover(E, Mx, My, 0.0, mac)) return false;
   Rates rt = rt_member;
-  if constexpr (LT) rt = local_rates(rt_member, *vis, N, mac);
+  if constexpr (EXT) {
+    if (!recover_model(N, E, Mx, My, 0.0, *ext, mac)) return false;
+    rt = local_rates(rt_member, *ext, N, mac);
+  } else {
+    if (!recover(E, Mx, My, 0.0, mac)) return false;
+  }
   double c7 = 0.0;
   if constexpr (CORR) c7 = d2q9::c7_row(mac, *fm, *fp);
   d2q9::collide_f(f, N, fs, mac, rt, ref);
@@ -295,14 +299,14 @@ __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt_me
   return true;
 }
 
-// Equilibrium deviations of a cell from its fields (Eqs. 7, 32, 33), FP64.
-__device__ __forceinline__ void equilibrium_dev(double n, double eps, double ux, double uy,
-                                                const Ref& ref, double (&f)[9],
+// Equilibrium deviations of a cell from its fields (Eqs. 7, 32, 33), FP64;
+// P is the pressure of the fields.
+__device__ __forceinline__ void equilibrium_dev(double n, double eps, double P, double ux,
+                                                double uy, const Ref& ref, double (&f)[9],
                                                 double (&g)[9]) {
   const double uu = ux * ux + uy * uy;
   const double gam2 = 1.0 / (1.0 - uu);
   const double N = n * sqrt(gam2);
-  const double P = eps / 3.0;
   const double sigma = (eps + P) * gam2;
 #pragma unroll
   for (int a = 0; a < 9; ++a) {

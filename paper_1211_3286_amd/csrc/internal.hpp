@@ -18,7 +18,7 @@ struct MemberDesc {
   int32_t pad;
   Rates rt;
   Ref ref;
-  Visc vis;  // relaxation times from eta/s (read by the LT kernels only)
+  Ext ext;  // eta/s relaxation times and equation of state (EXT kernels, init, export)
 };
 
 // Geometry of a single-lattice launch (the per-step fused kernel).
@@ -28,7 +28,7 @@ struct LatticeGeom {
   int64_t cs;  // plane stride in elements
   Rates rt;
   Ref ref;
-  Visc vis;  // relaxation times from eta/s (read by the LT kernels only)
+  Ext ext;  // eta/s relaxation times and equation of state (EXT kernels, init, export)
 };
 
 struct LatticeVariant {
@@ -50,14 +50,16 @@ constexpr int kRefBlocks = 64;
 hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const double* n0,
                               const double* eps0, const double* u0, int64_t ncells,
                               double* parts, hipStream_t s);
-// planar: also count cells with u_z != 0 (D2Q9 lattices carry no z velocity).
+// planar: also count cells with u_z != 0 (D2Q9 lattices carry no z velocity);
+// cells of members with a general equation of state also need eps > m n.
 hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
-                           int64_t ncells, int planar, unsigned long long* count, hipStream_t s);
+                           int64_t ncells, int planar, const MemberDesc* descs, int n_members,
+                           unsigned long long* count, hipStream_t s);
 hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
                        int n_members, const double* n0, const double* eps0, const double* u0,
                        int64_t ncells, hipStream_t s);
-// lt: relaxation times of each cell from eta/s (Rates.eta_s > 0).
-hipError_t launch_step_lattice(int precision, int variant, bool diag, bool lt, const void* src,
+// ext: the extended model (relaxation times from eta/s, general equation of state).
+hipError_t launch_step_lattice(int precision, int variant, bool diag, bool ext, const void* src,
                                void* dst, const LatticeGeom& g, double* partials,
                                unsigned long long* bad, hipStream_t s);
 int lattice_partials(int variant, const LatticeGeom& g);  // number of blocks
@@ -76,7 +78,7 @@ struct MemberLaunch {
   double* partials;
   unsigned long long* bad;
 };
-hipError_t member_kernel(int precision, int variant, bool lt, const void** func, dim3* block);
+hipError_t member_kernel(int precision, int variant, bool ext, const void** func, dim3* block);
 
 // Segmented persistent step: every member is cut into segments of whole
 // z-planes, one block per segment; a segment waits (per step) for the two
@@ -160,12 +162,12 @@ int d2q9_num_lattice_variants();
 int d2q9_lattice_partials(int variant, const LatticeGeom& g);
 const char* d2q9_lattice_kernel_name(int precision, int variant);
 // corr: apply the correction term of Eqs. (37)-(38) (flows along y);
-// lt: relaxation times of each cell from eta/s.
-hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, bool corr, bool lt,
+// ext: the extended model (relaxation times from eta/s, general equation of state).
+hipError_t d2q9_launch_step_lattice(int precision, int variant, bool diag, bool corr, bool ext,
                                     const void* src, void* dst, const LatticeGeom& g,
                                     double* partials, unsigned long long* bad, hipStream_t s);
 int d2q9_num_member_variants();
-hipError_t d2q9_member_kernel(int precision, int variant, bool corr, bool lt, const void** func,
+hipError_t d2q9_member_kernel(int precision, int variant, bool corr, bool ext, const void** func,
                               dim3* block);
 const char* d2q9_member_kernel_name(int precision, int variant);
 hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,

@@ -22,10 +22,10 @@ namespace {
 
 // -------------------------------------------------------------------------
 // Fused step on one lattice: grid (ceil(nx/BX), ceil(ny/BY), ceil(nz/CZ)),
-// block (BX, BY); each thread updates CZ cells along z. LT: relaxation times
+// block (BX, BY); each thread updates CZ cells along z. EXT: relaxation times
 // of each cell from eta/s.
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CZ, bool DIAG, bool LT>
+template <typename T, int BX, int BY, int CZ, bool DIAG, bool EXT>
 __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
         g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
       }
       Sums s;
-      const bool ok = collide<T, LT>(f, g, geo.rt, geo.ref, s, &geo.vis);
+      const bool ok = collide<T, EXT>(f, g, geo.rt, geo.ref, s, &geo.ext);
       nbad += ok ? 0 : 1;
       if (DIAG)
 #pragma unroll
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
 // grid-wide synchronisation exists). Each thread updates CPT cells per sweep,
 // interleaved by NT so every load instruction is coalesced.
 // -------------------------------------------------------------------------
-template <typename T, int NT, int CPT, bool LT>
+template <typename T, int NT, int CPT, bool EXT>
 __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
   const MemberDesc d = a.descs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
             g[q] = ld(src + (int64_t)(19 + q) * a.cs, off[q]);
           }
           Sums s;
-          const bool ok = collide<T, LT>(f, g, d.rt, d.ref, s, &d.vis);
+          const bool ok = collide<T, EXT>(f, g, d.rt, d.ref, s, &d.ext);
           nbad += ok ? 0 : 1;
 #pragma unroll
           for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
@@ -366,14 +366,17 @@ __global__ __launch_bounds__(64) void k_member_ref_final(MemberDesc* descs, cons
 
 __global__ __launch_bounds__(256) void k_validate(const double* n0, const double* eps0,
                                                   const double* u0, int64_t ncells, int planar,
+                                                  const MemberDesc* descs, int n_members,
                                                   unsigned long long* count) {
   int nb = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
        i += (int64_t)gridDim.x * 256) {
     const double ux = u0[i], uy = u0[ncells + i], uz = u0[2 * ncells + i];
     const double uu = ux * ux + uy * uy + uz * uz;
+    const Ext& x = descs[find_member(descs, n_members, i)].ext;
     const bool ok = (eps0[i] > 0.0) && (n0[i] >= 0.0) && (uu < 1.0) && (n0[i] < INFINITY) &&
-                    (eps0[i] < INFINITY) && (!planar || uz == 0.0);
+                    (eps0[i] < INFINITY) && (!planar || uz == 0.0) &&
+                    (!x.general_eos || eps0[i] - x.mass * n0[i] > 0.0);
     nb += ok ? 0 : 1;
   }
   if (nb) atomicAdd(count, (unsigned long long)nb);
@@ -386,9 +389,10 @@ __global__ __launch_bounds__(256) void k_init(T* state, int64_t cs, const Member
                                               int64_t ncells) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
        i += (int64_t)gridDim.x * 256) {
-    const Ref ref = descs[find_member(descs, n_members, i)].ref;
+    const MemberDesc& d = descs[find_member(descs, n_members, i)];
     double f[19], g[19];
-    equilibrium_dev(n0[i], eps0[i], u0[i], u0[ncells + i], u0[2 * ncells + i], ref, f, g);
+    const double P = pressure_of(eps0[i], n0[i], d.ext);
+    equilibrium_dev(n0[i], eps0[i], P, u0[i], u0[ncells + i], u0[2 * ncells + i], d.ref, f, g);
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
       state[a * cs + i] = (T)f[a];
@@ -406,7 +410,7 @@ __global__ __launch_bounds__(256) void k_export(const T* state, int64_t cs,
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
        i += (int64_t)gridDim.x * 256) {
-    const Ref ref = descs[find_member(descs, n_members, i)].ref;
+    const MemberDesc& d = descs[find_member(descs, n_members, i)];
     T f[19], g[19];
 #pragma unroll
     for (int a = 0; a < 19; ++a) {
@@ -414,20 +418,23 @@ __global__ __launch_bounds__(256) void k_export(const T* state, int64_t cs,
       g[a] = state[(19 + a) * cs + i];
     }
     double N, E, Mx, My, Mz, fs, gs;
-    cell_sums(f, g, ref, N, E, Mx, My, Mz, fs, gs);
+    cell_sums(f, g, d.ref, N, E, Mx, My, Mz, fs, gs);
     acc[0] += N;
     acc[1] += E;
     acc[2] += Mx;
     acc[3] += My;
     acc[4] += Mz;
     Macro m;
-    const bool ok = recover(E, Mx, My, Mz, m);
+    const bool gen = d.ext.general_eos != 0;
+    const bool ok = recover_model(N, E, Mx, My, Mz, d.ext, m);
     const double nan = __builtin_nan("");
-    const double e = ok ? 0.75 * m.sigma * (1.0 - m.u2) : nan;
+    // eps = (eps + P) - P; for P = eps/3 the closed form 3/4 sigma (1 - u^2)
+    const double e =
+        !ok ? nan : (gen ? m.sigma * (1.0 - m.u2) - m.P : 0.75 * m.sigma * (1.0 - m.u2));
     const double gm = ok ? 1.0 / sqrt(1.0 - m.u2) : nan;
     if (n) n[i] = ok ? N / gm : nan;
     if (eps) eps[i] = e;
-    if (P) P[i] = ok ? e / 3.0 : nan;
+    if (P) P[i] = !ok ? nan : (gen ? m.P : e / 3.0);
     if (gamma) gamma[i] = gm;
     if (u) {
       u[i] = ok ? m.ux : nan;
@@ -512,45 +519,45 @@ int grid_for(int64_t n) {
   return (int)b;
 }
 
-template <typename T, int BX, int BY, int CZ, bool LT>
+template <typename T, int BX, int BY, int CZ, bool EXT>
 hipError_t lat_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                       double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + CZ - 1) / CZ);
   if (diag)
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, LT>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, EXT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, LT>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, EXT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   return hipGetLastError();
 }
 
-template <typename T, bool LT>
+template <typename T, bool EXT>
 hipError_t lat_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
                         double* partials, unsigned long long* bad, hipStream_t s) {
   switch (v) {
-    case 0: return lat_launch<T, 64, 1, 1, LT>(diag, src, dst, g, partials, bad, s);
-    case 1: return lat_launch<T, 64, 4, 1, LT>(diag, src, dst, g, partials, bad, s);
-    case 2: return lat_launch<T, 128, 2, 1, LT>(diag, src, dst, g, partials, bad, s);
-    case 3: return lat_launch<T, 256, 1, 1, LT>(diag, src, dst, g, partials, bad, s);
-    case 4: return lat_launch<T, 64, 4, 2, LT>(diag, src, dst, g, partials, bad, s);
-    case 5: return lat_launch<T, 256, 1, 2, LT>(diag, src, dst, g, partials, bad, s);
-    case 6: return lat_launch<T, 128, 2, 4, LT>(diag, src, dst, g, partials, bad, s);
-    case 7: return lat_launch<T, 256, 1, 4, LT>(diag, src, dst, g, partials, bad, s);
+    case 0: return lat_launch<T, 64, 1, 1, EXT>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat_launch<T, 64, 4, 1, EXT>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat_launch<T, 128, 2, 1, EXT>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat_launch<T, 256, 1, 1, EXT>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat_launch<T, 64, 4, 2, EXT>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat_launch<T, 256, 1, 2, EXT>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat_launch<T, 128, 2, 4, EXT>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat_launch<T, 256, 1, 4, EXT>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T, bool LT>
+template <typename T, bool EXT>
 const void* mem_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_step_members<T, 256, 1, LT>;
-    case 1: return (const void*)&k_step_members<T, 512, 1, LT>;
-    case 2: return (const void*)&k_step_members<T, 1024, 1, LT>;
-    case 3: return (const void*)&k_step_members<T, 256, 2, LT>;
-    case 4: return (const void*)&k_step_members<T, 512, 2, LT>;
-    case 5: return (const void*)&k_step_members<T, 1024, 2, LT>;
+    case 0: return (const void*)&k_step_members<T, 256, 1, EXT>;
+    case 1: return (const void*)&k_step_members<T, 512, 1, EXT>;
+    case 2: return (const void*)&k_step_members<T, 1024, 1, EXT>;
+    case 3: return (const void*)&k_step_members<T, 256, 2, EXT>;
+    case 4: return (const void*)&k_step_members<T, 512, 2, EXT>;
+    case 5: return (const void*)&k_step_members<T, 1024, 2, EXT>;
   }
   return nullptr;
 }
@@ -644,9 +651,10 @@ hipError_t launch_member_refs(const MemberDesc* descs, int n_members, const doub
 }
 
 hipError_t launch_validate(const double* n0, const double* eps0, const double* u0,
-                           int64_t ncells, int planar, unsigned long long* count, hipStream_t s) {
+                           int64_t ncells, int planar, const MemberDesc* descs, int n_members,
+                           unsigned long long* count, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(grid_for(ncells)), dim3(256), 0, s, n0, eps0, u0, ncells,
-                     planar, count);
+                     planar, descs, n_members, count);
   return hipGetLastError();
 }
 
@@ -663,19 +671,19 @@ hipError_t launch_init(int precision, void* state, int64_t cs, const MemberDesc*
   return hipGetLastError();
 }
 
-hipError_t launch_step_lattice(int precision, int v, bool diag, bool lt, const void* src,
+hipError_t launch_step_lattice(int precision, int v, bool diag, bool ext, const void* src,
                                void* dst, const LatticeGeom& g, double* partials,
                                unsigned long long* bad, hipStream_t s) {
   if (precision)
-    return lt ? lat_dispatch<float, true>(v, diag, src, dst, g, partials, bad, s)
+    return ext ? lat_dispatch<float, true>(v, diag, src, dst, g, partials, bad, s)
               : lat_dispatch<float, false>(v, diag, src, dst, g, partials, bad, s);
-  return lt ? lat_dispatch<double, true>(v, diag, src, dst, g, partials, bad, s)
+  return ext ? lat_dispatch<double, true>(v, diag, src, dst, g, partials, bad, s)
             : lat_dispatch<double, false>(v, diag, src, dst, g, partials, bad, s);
 }
 
-hipError_t member_kernel(int precision, int v, bool lt, const void** func, dim3* block) {
+hipError_t member_kernel(int precision, int v, bool ext, const void** func, dim3* block) {
   if (v < 0 || v >= kNumMem) return hipErrorInvalidValue;
-  if (lt)
+  if (ext)
     *func = precision ? mem_func<float, true>(v) : mem_func<double, true>(v);
   else
     *func = precision ? mem_func<float, false>(v) : mem_func<double, false>(v);

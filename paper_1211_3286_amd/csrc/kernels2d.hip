@@ -36,7 +36,7 @@ __device__ __forceinline__ void c7_neighbours(const T* __restrict__ src, int64_t
 // correction of Eqs. (37)-(38) (each cell recovers its two y-neighbours from
 // their pulled populations: 18 more loads, mostly L2 hits).
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CY, bool DIAG, bool CORR, bool LT>
+template <typename T, int BX, int BY, int CY, bool DIAG, bool CORR, bool EXT>
 __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
       }
       Sums s;
       const bool ok =
-          d2q9::collide<T, CORR, LT>(f, g, geo.rt, geo.ref, s, &fm, &fp, &geo.vis);
+          d2q9::collide<T, CORR, EXT>(f, g, geo.rt, geo.ref, s, &fm, &fp, &geo.ext);
       nbad += ok ? 0 : 1;
       if (DIAG)
 #pragma unroll
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
 // Persistent step over a batch of D2Q9 members: one block per member, all
 // nsteps in the launch with a block barrier between steps.
 // -------------------------------------------------------------------------
-template <typename T, int NT, int CPT, bool CORR, bool LT>
+template <typename T, int NT, int CPT, bool CORR, bool EXT>
 __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
   const MemberDesc d = a.descs[blockIdx.x];
   const int tid = threadIdx.x;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
           }
           Sums s;
           const bool ok =
-              d2q9::collide<T, CORR, LT>(f, g, d.rt, d.ref, s, &fm, &fp, &d.vis);
+              d2q9::collide<T, CORR, EXT>(f, g, d.rt, d.ref, s, &fm, &fp, &d.ext);
           nbad += ok ? 0 : 1;
 #pragma unroll
           for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
@@ -167,9 +167,10 @@ __global__ __launch_bounds__(256) void k_d2q9_init(T* state, int64_t cs, const M
                                                    int64_t ncells) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
        i += (int64_t)gridDim.x * 256) {
-    const Ref ref = descs[member_of(descs, n_members, i)].ref;
+    const MemberDesc& d = descs[member_of(descs, n_members, i)];
     double f[9], g[9];
-    d2q9::equilibrium_dev(n0[i], eps0[i], u0[i], u0[ncells + i], ref, f, g);
+    const double P = pressure_of(eps0[i], n0[i], d.ext);
+    d2q9::equilibrium_dev(n0[i], eps0[i], P, u0[i], u0[ncells + i], d.ref, f, g);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
       state[a * cs + i] = (T)f[a];
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void k_d2q9_export(const T* state, int64_t cs,
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < ncells;
        i += (int64_t)gridDim.x * 256) {
-    const Ref ref = descs[member_of(descs, n_members, i)].ref;
+    const MemberDesc& d = descs[member_of(descs, n_members, i)];
     T f[9], g[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -195,19 +196,21 @@ __global__ __launch_bounds__(256) void k_d2q9_export(const T* state, int64_t cs,
       g[a] = state[(9 + a) * cs + i];
     }
     double N, E, Mx, My, fs, gs;
-    d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
+    d2q9::cell_sums(f, g, d.ref, N, E, Mx, My, fs, gs);
     acc[0] += N;
     acc[1] += E;
     acc[2] += Mx;
     acc[3] += My;
     Macro m;
-    const bool ok = recover(E, Mx, My, 0.0, m);
+    const bool gen = d.ext.general_eos != 0;
+    const bool ok = recover_model(N, E, Mx, My, 0.0, d.ext, m);
     const double nan = __builtin_nan("");
-    const double e = ok ? 0.75 * m.sigma * (1.0 - m.u2) : nan;
+    const double e =
+        !ok ? nan : (gen ? m.sigma * (1.0 - m.u2) - m.P : 0.75 * m.sigma * (1.0 - m.u2));
     const double gm = ok ? 1.0 / sqrt(1.0 - m.u2) : nan;
     if (n) n[i] = ok ? N / gm : nan;
     if (eps) eps[i] = e;
-    if (P) P[i] = ok ? e / 3.0 : nan;
+    if (P) P[i] = !ok ? nan : (gen ? m.P : e / 3.0);
     if (gamma) gamma[i] = gm;
     if (u) {
       u[i] = ok ? m.ux : nan;
@@ -251,44 +254,44 @@ int grid2_for(int64_t n) {
   return (int)b;
 }
 
-template <typename T, int BX, int BY, int CY, bool CORR, bool LT>
+template <typename T, int BX, int BY, int CY, bool CORR, bool EXT>
 hipError_t lat2_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                        double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY * CY - 1) / (BY * CY), 1);
   if (diag)
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR, LT>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR, EXT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR, LT>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR, EXT>), grid, block, 0, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   return hipGetLastError();
 }
 
-template <typename T, bool CORR, bool LT>
+template <typename T, bool CORR, bool EXT>
 hipError_t lat2_dispatch(int v, bool diag, const void* src, void* dst, const LatticeGeom& g,
                          double* partials, unsigned long long* bad, hipStream_t s) {
   switch (v) {
-    case 0: return lat2_launch<T, 64, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 1: return lat2_launch<T, 128, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 2: return lat2_launch<T, 256, 1, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 3: return lat2_launch<T, 64, 4, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 4: return lat2_launch<T, 128, 2, 1, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 5: return lat2_launch<T, 256, 1, 2, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 6: return lat2_launch<T, 256, 1, 4, CORR, LT>(diag, src, dst, g, partials, bad, s);
-    case 7: return lat2_launch<T, 128, 2, 4, CORR, LT>(diag, src, dst, g, partials, bad, s);
+    case 0: return lat2_launch<T, 64, 1, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 1: return lat2_launch<T, 128, 1, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 2: return lat2_launch<T, 256, 1, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 3: return lat2_launch<T, 64, 4, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 4: return lat2_launch<T, 128, 2, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 5: return lat2_launch<T, 256, 1, 2, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 6: return lat2_launch<T, 256, 1, 4, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 7: return lat2_launch<T, 128, 2, 4, CORR, EXT>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename T, bool CORR, bool LT>
+template <typename T, bool CORR, bool EXT>
 const void* mem2_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR, LT>;
-    case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR, LT>;
-    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR, LT>;
-    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR, LT>;
-    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR, LT>;
+    case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR, EXT>;
+    case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR, EXT>;
+    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR, EXT>;
+    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR, EXT>;
+    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR, EXT>;
   }
   return nullptr;
 }
@@ -317,35 +320,35 @@ const char* d2q9_lattice_kernel_name(int precision, int v) {
 }
 
 template <typename T>
-hipError_t lat2_modes(int v, bool diag, bool corr, bool lt, const void* src, void* dst,
+hipError_t lat2_modes(int v, bool diag, bool corr, bool ext, const void* src, void* dst,
                       const LatticeGeom& g, double* partials, unsigned long long* bad,
                       hipStream_t s) {
   if (corr)
-    return lt ? lat2_dispatch<T, true, true>(v, diag, src, dst, g, partials, bad, s)
+    return ext ? lat2_dispatch<T, true, true>(v, diag, src, dst, g, partials, bad, s)
               : lat2_dispatch<T, true, false>(v, diag, src, dst, g, partials, bad, s);
-  return lt ? lat2_dispatch<T, false, true>(v, diag, src, dst, g, partials, bad, s)
+  return ext ? lat2_dispatch<T, false, true>(v, diag, src, dst, g, partials, bad, s)
             : lat2_dispatch<T, false, false>(v, diag, src, dst, g, partials, bad, s);
 }
 
-hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, bool corr, bool lt,
+hipError_t d2q9_launch_step_lattice(int precision, int v, bool diag, bool corr, bool ext,
                                     const void* src, void* dst, const LatticeGeom& g,
                                     double* partials, unsigned long long* bad, hipStream_t s) {
-  if (precision) return lat2_modes<float>(v, diag, corr, lt, src, dst, g, partials, bad, s);
-  return lat2_modes<double>(v, diag, corr, lt, src, dst, g, partials, bad, s);
+  if (precision) return lat2_modes<float>(v, diag, corr, ext, src, dst, g, partials, bad, s);
+  return lat2_modes<double>(v, diag, corr, ext, src, dst, g, partials, bad, s);
 }
 
 int d2q9_num_member_variants() { return kNumMem2; }
 
 template <typename T>
-const void* mem2_modes(int v, bool corr, bool lt) {
-  if (corr) return lt ? mem2_func<T, true, true>(v) : mem2_func<T, true, false>(v);
-  return lt ? mem2_func<T, false, true>(v) : mem2_func<T, false, false>(v);
+const void* mem2_modes(int v, bool corr, bool ext) {
+  if (corr) return ext ? mem2_func<T, true, true>(v) : mem2_func<T, true, false>(v);
+  return ext ? mem2_func<T, false, true>(v) : mem2_func<T, false, false>(v);
 }
 
-hipError_t d2q9_member_kernel(int precision, int v, bool corr, bool lt, const void** func,
+hipError_t d2q9_member_kernel(int precision, int v, bool corr, bool ext, const void** func,
                               dim3* block) {
   if (v < 0 || v >= kNumMem2) return hipErrorInvalidValue;
-  *func = precision ? mem2_modes<float>(v, corr, lt) : mem2_modes<double>(v, corr, lt);
+  *func = precision ? mem2_modes<float>(v, corr, ext) : mem2_modes<double>(v, corr, ext);
   *block = dim3(kMem2[v].nt, 1, 1);
   return hipSuccess;
 }

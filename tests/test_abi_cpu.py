@@ -178,3 +178,18 @@ def test_correction_option_validated():
     assert _size([_p(**d2)], rlb.options(lattice=rlb.D2Q9, correction=1))[0] == 0
     assert _size([_p(**d2)], rlb.options(lattice=rlb.D2Q9, correction=2))[0] == -1
     assert _size([_p()], rlb.options(correction=1))[0] == -7
+
+
+def test_equation_of_state_parameters_validated():
+    assert _size([_p(eos_gamma=5 / 3, mass=0.5)], rlb.options())[0] == 0
+    assert _size([_p(eos_gamma=2.5)], rlb.options())[0] == -1
+    assert _size([_p(eos_gamma=1.0)], rlb.options())[0] == -1
+    assert _size([_p(mass=-1.0)], rlb.options())[0] == -1
+    assert _size([_p(eos_gamma=5 / 3)], rlb.options(rlb.FP32, 10, 100))[0] == -7
+    d2 = dict(nx=4, ny=8, nz=1, bc=(0, 1, 0))
+    assert _size([_p(mass=0.1, **d2)], rlb.options(lattice=rlb.D2Q9, correction=1))[0] == -7
+    # every input cell needs eps > m n (checked on host fields before device work)
+    p = _p(eos_gamma=5 / 3, mass=2.0)
+    opt = rlb.options()
+    _, need = _size([p], opt)
+    assert _init([p], _fields(96, eps=1.0, n=1.0), 1 << 40, need, opt) == -3

@@ -62,6 +62,10 @@ class Params:
     a_e: float = 0.0
     a_eps: float = 0.0
     a_q: float = 0.0
+    # Equation of state P = (Gamma - 1)(eps - m n); eos_gamma = 0 (or 4/3) with
+    # mass = 0 is the paper's P = eps/3.
+    eos_gamma: float = 0.0
+    mass: float = 0.0
 
     @property
     def shape(self) -> Tuple[int, int, int]:
