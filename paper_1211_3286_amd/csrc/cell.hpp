@@ -157,31 +157,41 @@ __device__ __forceinline__ bool recover_general(double N, double E, double Mx, d
   const double G = x.eos_gamma, c = (x.eos_gamma - 1.0) / x.eos_gamma, mass = x.mass;
   const double M2 = Mx * Mx + My * My + Mz * Mz;
   const bool ok0 = (E > 0.0) && (M2 < E * E) && (N >= 0.0);
-  const double Es = ok0 ? E : 1.0, M2s = ok0 ? M2 : 0.0, Ns = ok0 ? N : 0.0;
+  const double Es = ok0 ? E : 1.0, M2s = ok0 ? M2 : 0.0, mN = ok0 ? mass * N : 0.0;
   double lo = sqrt(M2s), hi = G * Es;
-  double z = 0.5 * (G * Es + sqrt(fmax(G * G * Es * Es - 4.0 * (G - 1.0) * M2s, 0.0)));
-  z = fmin(fmax(z, lo), hi);
+  // start from the root at rest, z = Gamma E - (Gamma - 1) m N (exact for M = 0)
+  double z = fmin(fmax(G * Es - (G - 1.0) * mN, lo), hi);
+  // F is evaluated near double precision: 1/z from the hardware reciprocal plus
+  // one Newton-Raphson refinement (which squares its relative error) and an
+  // IEEE square root. The derivative only sets the step, so it uses the
+  // unrefined reciprocal square root; the bracket keeps every step safe.
+  double inv_z = 0.0;
   for (int it = 0; it < 64; ++it) {
-    const double x2 = M2s / (z * z);
+    const double r = __builtin_amdgcn_rcp(z);
+    inv_z = fma(fma(-z, r, 1.0), r, r);
+    const double Mz_ = M2s * inv_z;
+    const double x2 = Mz_ * inv_z;
     const double sq = sqrt(1.0 - x2);
-    const double Fz = z - Es - c * ((z - M2s / z) - mass * Ns * sq);
+    const double Fz = z - Es - c * ((z - Mz_) - mN * sq);
     if (Fz > 0.0)
       hi = z;
     else
       lo = z;
-    const double dF = 1.0 - c * (1.0 + x2 - mass * Ns * (x2 / z) / sq);
-    double zn = z - Fz / dF;
+    const double dF = 1.0 - c * (1.0 + x2 - mN * x2 * inv_z * __builtin_amdgcn_rsq(1.0 - x2));
+    double zn = z - Fz * __builtin_amdgcn_rcp(dF);
     if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
     const bool done = fabs(zn - z) <= 1e-15 * z;
     z = zn;
     if (done) break;
   }
-  const double sq = sqrt(1.0 - M2s / (z * z));
-  const double P = c * ((z - M2s / z) - mass * Ns * sq);
+  const double r = __builtin_amdgcn_rcp(z);
+  inv_z = fma(fma(-z, r, 1.0), r, r);
+  const double sq = sqrt(1.0 - M2s * inv_z * inv_z);
+  const double P = c * ((z - M2s * inv_z) - mN * sq);
   const bool ok = ok0 && (P > 0.0);
-  m.ux = ok ? Mx / z : 0.0;
-  m.uy = ok ? My / z : 0.0;
-  m.uz = ok ? Mz / z : 0.0;
+  m.ux = ok ? Mx * inv_z : 0.0;
+  m.uy = ok ? My * inv_z : 0.0;
+  m.uz = ok ? Mz * inv_z : 0.0;
   m.u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
   m.sigma = ok ? z : 4.0 / 3.0;
   m.P = ok ? P : 1.0 / 3.0;
