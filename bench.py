@@ -105,7 +105,7 @@ def bench_lattice(torch, rlb, wl, n: int, precision: int, steps: int, warmup: in
     prob = wl.random_modes(n, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
                            tau_eps=0.7, tau_f=0.8)
     sim = rlb.from_problems(prob, precision=precision, diag_every=diag_every)
-    tune = sim.tune(trial_steps=3)
+    tune = sim.tune(trial_steps=10)
     log("tuned", tune["name"], {k: round(v, 4) for k, v in tune["ms_per_step"].items()})
     s0 = sim.sums()
     ms, wall = time_steps(torch, sim, steps, warmup)
@@ -222,7 +222,7 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
     for prec, name, corr in ((rlb.FP32, "fp32", 0), (rlb.FP64, "fp64", 0),
                              (rlb.FP32, "fp32_c7", 1)):
         sim = rlb.from_problems(prob, precision=prec, diag_every=50, correction=corr)
-        tune = sim.tune(trial_steps=3)
+        tune = sim.tune(trial_steps=10)
         s0 = sim.sums()
         ms, _ = time_steps(torch, sim, steps, warmup)
         s1 = sim.sums()
@@ -267,7 +267,7 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
                            tau_eps=0.7, tau_f=0.8)
     prob.params.eta_s, prob.params.a_e, prob.params.a_eps = 0.1, 0.2, 0.5
     sim = rlb.from_problems(prob, precision=rlb.FP32, diag_every=50)
-    tune = sim.tune(trial_steps=3)
+    tune = sim.tune(trial_steps=10)
     ms, _ = time_steps(torch, sim, steps, warmup)
     cells = prob.params.ncells
     gbs = 304 * cells / (ms * 1e-3) / 1e9
@@ -279,7 +279,7 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
     prob.params.eta_s = 0.0
     prob.params.eos_gamma, prob.params.mass = 1.5, 0.6
     sim = rlb.from_problems(prob, precision=rlb.FP32, diag_every=50)
-    tune = sim.tune(trial_steps=3)
+    tune = sim.tune(trial_steps=10)
     ms, _ = time_steps(torch, sim, steps, warmup)
     gbs = 304 * cells / (ms * 1e-3) / 1e9
     out["general_eos"] = {"eos": "Gamma 1.5, m 0.6", "ms_per_step": ms,
@@ -321,7 +321,7 @@ def cpu_baseline(prob, seconds: float):
                       f"{prob.params.nz} lattice (after 1 untimed step), {dt:.1f} s"}
 
 
-def summarize_trace(csv_path: str, command: str) -> str:
+def summarize_trace(csv_path: str, command: str, top: int = 25, min_launches: int = 40) -> str:
     """Markdown tables of a rocprofv3 --kernel-trace --stats run: the
     kernel_stats.csv summary, and (from the kernel_trace.csv beside it) the
     step kernels split by launch grid, since one kernel serves several
@@ -336,27 +336,37 @@ def summarize_trace(csv_path: str, command: str) -> str:
 
     rows = list(csv.DictReader(open(csv_path)))
     out = [f"Command: `{command}`", "",
+           f"The {top} kernels with the most total time:", "",
            "| kernel | calls | average (us) | min (us) | max (us) | total (ms) | % |",
            "|---|---|---|---|---|---|---|"]
+    rest = rows[top:]
+    rows = rows[:top]
     for r in rows:
         out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    if rest:
+        out.append(f"| {len(rest)} more kernels | {sum(int(r['Calls']) for r in rest)} | | | | "
+                   f"{sum(float(r['TotalDurationNs']) for r in rest) / 1e6:.2f} | "
+                   f"{sum(float(r['Percentage']) for r in rest):.1f} |")
     trace = csv_path.replace("kernel_stats.csv", "kernel_trace.csv")
     if trace != csv_path and os.path.exists(trace):
         groups = collections.defaultdict(list)
         for r in csv.DictReader(open(trace)):
             name = short(r["Kernel_Name"])
-            if not name.startswith(("k_step", "k_adj_step", "k_gstep")):
+            if not name.startswith(("k_step", "k_adj_step", "k_gstep", "k_d2q9_lattice", "k_d2q9_members")):
                 continue
             grid = "x".join(r[f"Grid_Size_{a}"] for a in "XYZ")
             block = "x".join(r[f"Workgroup_Size_{a}"] for a in "XYZ")
             groups[(name, grid, block)].append(
                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-        out += ["", "Step kernels by launch grid (threads), from the kernel_trace.csv of the same run:", "",
+        out += ["", f"Step kernels by launch grid (threads), from the kernel_trace.csv of the same "
+                f"run ({min_launches} or more launches):", "",
                 "| kernel | grid | block | launches | average (us) | min (us) | max (us) |",
                 "|---|---|---|---|---|---|---|"]
         for (name, grid, block), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+            if len(d) < min_launches:
+                continue
             out.append(f"| `{name}` | {grid} | {block} | {len(d)} | {sum(d) / len(d):.1f} | "
                        f"{min(d):.1f} | {max(d):.1f} |")
     return "\n".join(out) + "\n"
