@@ -18,7 +18,10 @@ Prints one JSON line. ``value`` is MLUPS (million lattice-cell updates per
 second) with the populations resident in HBM; ``roofline`` prices the fused
 kernel at its algorithmic traffic (2 x 38 populations per cell update);
 ``cpu_baseline`` times the FP64 CPU oracle on a bounded sample of the same
-workload on the host cores.
+workload on the host cores; ``error_vs_oracle`` then runs the GPU path from
+the same input for the same number of steps, in the kernel variants that were
+timed, and gives its max-norm errors against that oracle state over all
+cells.
 """
 
 from __future__ import annotations
@@ -304,7 +307,8 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
 
 
 def cpu_baseline(prob, seconds: float):
-    """The FP64 oracle on the host cores, on whole steps of the same lattice."""
+    """The FP64 oracle on the host cores, on whole steps of the same lattice.
+    Returns the baseline record and the oracle state it reached."""
     import oracle
     threads = oracle.max_threads()
     st = oracle.State.init(prob)
@@ -316,9 +320,40 @@ def cpu_baseline(prob, seconds: float):
     st.step(n)
     dt = time.perf_counter() - t0
     cells = prob.params.ncells
-    return {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{n} FP64 steps of the full {prob.params.nx}x{prob.params.ny}x"
-                      f"{prob.params.nz} lattice (after 1 untimed step), {dt:.1f} s"}
+    rec = {"value": cells * n / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{n} FP64 steps of the full {prob.params.nx}x{prob.params.ny}x"
+                     f"{prob.params.nz} lattice (after 1 untimed step), {dt:.1f} s"}
+    return rec, st, n + 1
+
+
+def error_vs_oracle(torch, rlb, prob, st, steps: int, kernels, diag_every: int):
+    """Max-norm errors of the GPU path against the oracle state of the CPU
+    baseline (the same input, the same number of steps), over every cell:
+    max|a - b| / max|b| for populations and n, eps; max|a - b| for u. Each GPU
+    run uses the kernel variant the benchmark timed for that precision."""
+    import numpy as np
+    F = st.fields()
+    ref = {"f": st.f, "g": st.g, "n": F["n"], "eps": F["eps"], "u": F["u"]}
+    out = {"steps": steps, "cells": prob.params.ncells}
+    for prec, kernel in kernels:
+        sim = rlb.from_problems(prob, precision=prec, diag_every=diag_every)
+        sim.variant = sim.variants().index(kernel)
+        sim.step(steps)
+        f, g = sim.populations()
+        m = sim.moments(allow_unphysical=True)
+        gpu = {"f": f, "g": g, "n": m["n"], "eps": m["eps"], "u": m["u"]}
+        err = {}
+        for k, a in gpu.items():
+            b = torch.from_numpy(np.ascontiguousarray(ref[k])).to(a.device).reshape(a.shape)
+            d = (a - b).abs().max().item()
+            err[k] = d if k == "u" else d / b.abs().max().item()
+            del b
+        err["kernel"] = kernel
+        err["inadmissible"] = m["bad"]
+        out["fp32" if prec == rlb.FP32 else "fp64"] = err
+        del f, g, m, gpu
+        sim.close()
+    return out
 
 
 def summarize_trace(csv_path: str, command: str, top: int = 25, min_launches: int = 40) -> str:
@@ -474,14 +509,28 @@ def main():
         log("d2q9", forms["d2q9"])
         forms["eta_s"] = bench_eta_s(torch, rlb, wl)
         log("eta_s", forms["eta_s"])
+        # the runtime's own device-to-device copy of the bytes one FP32 step
+        # moves (38 x 4 B per cell read, the same written): a practical
+        # bandwidth ceiling to read the roofline fraction against
+        cc = copy_calibration(torch, nbytes=38 * 4 * head["cells"], reps=20)
+        cc["step_fraction_of_copy"] = head["achieved_gbs"] / cc["gbs"]
+        forms["copy_ceiling"] = cc
+        log("copy ceiling", cc)
     if args.copy_calibration:
         forms["copy_calibration"] = copy_calibration(torch)
         log("copy", forms["copy_calibration"])
-    cpu = None
+    cpu = errors = None
     if not args.no_cpu:
         log("cpu baseline ...")
-        cpu = cpu_baseline(head["problem"], args.cpu_seconds)
+        cpu, ost, osteps = cpu_baseline(head["problem"], args.cpu_seconds)
         log("cpu", cpu)
+        kernels = [(prec, head["kernel"])]
+        if not args.no_forms:
+            kernels.append((other, forms["fp64" if other == rlb.FP64 else "fp32"]["kernel"]))
+        errors = error_vs_oracle(torch, rlb, head["problem"], ost, osteps, kernels,
+                                 args.diag_every)
+        log("error vs oracle", errors)
+        del ost
     p = head["problem"].params
     line = {
         "metric": METRIC, "value": round(head["mlups"], 1), "unit": "MLUPS", "n_gpus": 1,
@@ -492,7 +541,7 @@ def main():
                    "lattice": "D3Q19 f+g", "cells": head["cells"], "tau_v": p.tau_v,
                    "tau_e": p.tau_e, "tau_eps": p.tau_eps, "tau_f": p.tau_f,
                    "recovery": "fp64", "diag_every": args.diag_every},
-        "roofline": roof, "cpu_baseline": cpu,
+        "roofline": roof, "cpu_baseline": cpu, "error_vs_oracle": errors,
         "conservation_drift": head["conservation_drift"], "inadmissible": head["inadmissible"],
         "forms": forms,
     }

@@ -150,8 +150,12 @@ __device__ __forceinline__ bool recover(double E, double Mx, double My, double M
 // Eq. (10) gives z = E + P, u = M / z, eps + P = z - |M|^2/z, n = N / gamma:
 //   F(z) = z - E - c [(z - |M|^2/z) - m N sqrt(1 - |M|^2/z^2)] = 0, c = (Gamma-1)/Gamma.
 // F increases on (|M|, Gamma E] with F(|M|) < 0 <= F(Gamma E): Newton from the
-// massless root, kept inside the shrinking bracket (bisection when a step
-// leaves it), FP64. A cell needs E > 0, |M| < E, N >= 0 and P > 0.
+// root at rest, kept inside the shrinking bracket (bisection when a step
+// leaves it), FP64. A step at the rounding level ends the iteration before
+// the bracket test: Newton approaching from one side leaves the other end of
+// the bracket where it started, and such a step lands on the near end, so
+// testing it first would throw z back to the middle of the initial bracket.
+// A cell needs E > 0, |M| < E, N >= 0 and P > 0.
 __device__ __forceinline__ bool recover_general(double N, double E, double Mx, double My,
                                                 double Mz, const Ext& x, Macro& m) {
   const double G = x.eos_gamma, c = (x.eos_gamma - 1.0) / x.eos_gamma, mass = x.mass;
@@ -179,8 +183,8 @@ __device__ __forceinline__ bool recover_general(double N, double E, double Mx, d
       lo = z;
     const double dF = 1.0 - c * (1.0 + x2 - mN * x2 * inv_z * __builtin_amdgcn_rsq(1.0 - x2));
     double zn = z - Fz * __builtin_amdgcn_rcp(dF);
-    if (!(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
     const bool done = fabs(zn - z) <= 1e-15 * z;
+    if (!done && !(zn > lo && zn < hi)) zn = 0.5 * (lo + hi);
     z = zn;
     if (done) break;
   }

@@ -3,9 +3,14 @@
 After K steps a cell depends only on its (2K+1)^3 neighbourhood, so the
 oracle computes sampled cells one by one on that window of the same seeded
 initial fields (periodic axes wrap; a clamped axis is cut at the real face,
-where the window keeps the zero-gradient rule). The GPU runs the whole
-lattice in the launch configuration the benchmark times (autotuned).
-Sampled cells cover corners, edges, faces and the interior.
+where the window keeps the zero-gradient rule). With the correction term of
+Eqs. (37)-(38) a step also reads the fields of the y-neighbours after their
+pull, so the cone widens by two cells a step and the window is (4K+1) wide.
+The GPU runs the whole lattice in the launch configuration the benchmark
+times (autotuned). Sampled cells cover corners, edges, faces and the
+interior. Every timed form is covered: the FP32/FP64 step and the blast,
+relaxation times from eta/s, the general equation of state, and the D2Q9
+model with the correction term.
 """
 
 import numpy as np
@@ -25,12 +30,13 @@ def _samples(shape, rng, n_random=6, extra=()):
     pts = {(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, nx // 2), (nz // 2, 0, nx - 1),
            (nz // 2, ny // 2, nx // 2), (1, ny - 2, 1)}
     pts.update(extra)
+    pts = {tuple(min(c, d - 1) for c, d in zip(p, shape)) for p in pts}  # nz = 1 lattices
     for _ in range(n_random):
         pts.add(tuple(int(rng.integers(0, d)) for d in shape))
     return sorted(pts)
 
 
-def _check(prob, prec, K, tol, tune=True, extra=()):
+def _check(prob, prec, K, tol, tune=True, extra=(), radius=1):
     import torch
     import paper_1211_3286_amd as rlb
     sh = prob.params.shape
@@ -50,7 +56,7 @@ def _check(prob, prec, K, tol, tune=True, extra=()):
         idx = (cell[0] * sh[1] + cell[1]) * sh[2] + cell[2]
         gf = f[:, idx].cpu().numpy()
         gg = g[:, idx].cpu().numpy()
-        sub, loc = wl.window(prob, cell, K)
+        sub, loc = wl.window(prob, cell, radius * K)
         st = oracle.run(sub, K)
         of = st.f[(slice(None),) + loc]
         og = st.g[(slice(None),) + loc]
@@ -106,3 +112,47 @@ def test_blast_512cubed_fp32():
     prob = wl.blast(512)
     worst, _, bad = _check(prob, FP32, 3, 1e-5)
     assert worst < 1e-5
+
+
+def _random_flow(n=256, **kw):
+    prob = wl.random_modes(n, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    for k, v in kw.items():
+        setattr(prob.params, k, v)
+    return prob
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tol", [(FP32, 1e-5), (FP64, 1e-12)])
+def test_eta_s_256cubed(prec, tol):
+    """Relaxation times set per cell from eta/s = 0.1 (tau_e, tau_eps tied to
+    tau_v with ratios 0.2 and 0.5), the 256^3 lattice the benchmark times."""
+    prob = _random_flow(eta_s=0.1, a_e=0.2, a_eps=0.5)
+    worst, drift, bad = _check(prob, prec, 4, tol)
+    assert worst < tol and bad == 0
+    assert drift < (1e-10 if prec == FP32 else 1e-13)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tol", [(FP32, 1e-5), (FP64, 1e-12)])
+def test_general_eos_256cubed(prec, tol):
+    """P = (Gamma - 1)(eps - m n) with Gamma = 1.5, m = 0.6 (Newton recovery
+    per cell) on the 256^3 lattice the benchmark times."""
+    prob = _random_flow(eos_gamma=1.5, mass=0.6)
+    worst, drift, bad = _check(prob, prec, 4, tol)
+    assert worst < tol and bad == 0
+    assert drift < (1e-10 if prec == FP32 else 1e-13)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,tol", [(FP32, 1e-5), (FP64, 1e-12)])
+def test_d2q9_corrected_4096_squared(prec, tol):
+    """The D2Q9 model with the correction term on the 4096 x 4096 periodic
+    lattice the benchmark times."""
+    prob = wl.random_modes(4096, 4096, 1, seed=1211, umax=0.1, amp=0.05, tau_v=0.8,
+                           tau_e=0.55, tau_eps=0.7, tau_f=0.8)
+    prob.params.lattice = "d2q9"
+    prob.params.correction = 1
+    worst, drift, bad = _check(prob, prec, 4, tol, radius=2)
+    assert worst < tol and bad == 0
+    assert drift < (1e-10 if prec == FP32 else 1e-13)

@@ -153,3 +153,23 @@ def test_mirror_symmetry(orc):
     eps, uy = F["eps"][0, :, 0], F["u"][1, 0, :, 0]
     assert np.abs(eps - eps[::-1]).max() < 1e-12 * eps.max()
     assert np.abs(uy + uy[::-1]).max() < 1e-12
+
+
+def test_dependence_cone_is_two_cells_a_step(orc):
+    """A corrected step reads the y-neighbours' fields after their pull, so
+    after K steps a cell depends on cells up to 2K away along y: a window of
+    half-width 2K reproduces the full run exactly, one of half-width K does
+    not (the full-size GPU tests rely on the former)."""
+    prob = wl.random_modes(48, 40, 1, seed=7, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    prob.params.lattice = "d2q9"
+    prob.params.correction = 1
+    K = 3
+    full = orc.run(prob, K)
+    for radius, exact in ((2, True), (1, False)):
+        d = 0.0
+        for c in ((0, 5, 7), (0, 20, 30), (0, 39, 0)):
+            sub, loc = wl.window(prob, c, radius * K)
+            st = orc.run(sub, K)
+            d = max(d, np.abs(st.g[(slice(None),) + loc] - full.g[(slice(None),) + c]).max())
+        assert (d == 0.0) == exact, (radius, d)
