@@ -157,15 +157,19 @@ rlb_status rlb_workspace_size(const rlb_params* members, int32_t n_members,
                               const rlb_options* opt, size_t* bytes);
 
 /* Create a simulation and set the state at t = 0 to the equilibria of the
- * initial fields: f = f_eq(n0, u0) (Eq. 7), g = g_eq(eps0, eps0/3, u0)
- * (Eqs. 8-9).
+ * initial fields: f = f_eq(n0, u0) (Eq. 7), g = g_eq(eps0, P0, u0)
+ * (Eqs. 8-9), P0 = eps0/3 (or the general equation of state of rlb_params).
  *   n0, eps0: ncells doubles each; u0: 3 * ncells doubles (u_x, u_y, u_z planes).
  *   fields_on_device: 1 if n0/eps0/u0 are device pointers, 0 for host.
  *   workspace: device, 256-byte aligned, at least rlb_workspace_size bytes.
  *   hip_stream: hipStream_t (NULL = null stream); every later call uses it.
- * Validation (before any device work): dims >= 1, bc in {0, 1}, every tau > 1/2
- * and finite; every cell n0 >= 0, eps0 > 0, |u0| < 1 (finite). On error *out is
- * NULL. The fields are only read during this call. */
+ * Validation (before any state is written): dims >= 1, bc in {0, 1}, every
+ * tau > 1/2 and finite, the eta/s and equation-of-state parameters in range
+ * (RLB_E_ARG, RLB_E_TAU); every cell n0 >= 0, eps0 > 0, |u0| < 1 (finite),
+ * eps0 > mass n0 under the general equation of state, u_z = 0 on D2Q9
+ * (RLB_E_UNPHYSICAL); a member of 2^31 cells or more, or an option
+ * combination listed as unsupported above (RLB_E_UNSUPPORTED). On error *out
+ * is NULL. The fields are only read during this call. */
 rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_members,
                     const rlb_options* opt, const double* n0, const double* eps0,
                     const double* u0, int32_t fields_on_device, void* workspace,
