@@ -105,8 +105,8 @@ typedef struct {
    * viscosity transformation of Secs. IV and V.A, 1 = none), and for x in
    * {f, e, eps, q} with a_x > 0: tau_x - 1/2 = a_x (tau_v - 1/2); tau_q <= 0
    * ties tau_q to the local tau_v. A cell with n <= 0 or P <= 0 uses the
-   * fixed taus, which must be valid in any case. Not with a tape, tube rounds
-   * or segmented launches (RLB_E_UNSUPPORTED). T = P / n is the ideal-gas
+   * fixed taus, which must be valid in any case. Not with a tape or the
+   * segmented launches (RLB_E_UNSUPPORTED). T = P / n is the ideal-gas
    * temperature, also under the general equation of state below. */
   double eta_over_s;   /* >= 0 */
   double kappa;        /* > 0 when eta_over_s > 0 */
@@ -117,8 +117,8 @@ typedef struct {
    * leaves one equation for z = (eps + P) gamma^2, solved per cell by a
    * bracketed Newton iteration in FP64. eos_gamma in (1, 2] (or 0), mass >= 0;
    * every input cell needs eps > mass n; cells whose root gives P <= 0 are
-   * inadmissible. Not with a tape, the correction term, tube rounds or
-   * segmented launches (RLB_E_UNSUPPORTED). */
+   * inadmissible. Not with a tape, the correction term or the segmented
+   * launches (RLB_E_UNSUPPORTED). */
   double eos_gamma;
   double mass;
 } rlb_params;

@@ -327,7 +327,7 @@ rlb_status build_tube_segments(rlb_sim* h, int tv) {
 rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
                         int diag_every, int64_t step0, bool* flip) {
   const int tv = tube_index(variant);
-  if (!h->all_tubes || h->ext) return RLB_E_UNSUPPORTED;  // fixed relaxation times only
+  if (!h->all_tubes) return RLB_E_UNSUPPORTED;
   if (h->seg_built != 1000 + tv) {
     rlb_status st = build_tube_segments(h, tv);
     if (st != RLB_OK) return st;
@@ -335,7 +335,7 @@ rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void*
   const rlb::TubeVariant v = rlb::tube_variant(tv);
   const void* func;
   dim3 block;
-  RLB_HIP(rlb::tube_kernel(h->precision, tv, &func, &block));
+  RLB_HIP(rlb::tube_kernel(h->precision, tv, h->ext, &func, &block));
   const int rounds = (nsteps + v.halo - 1) / v.halo;
   if (h->tgexec) {  // the previous chain may still run: let it finish first
     RLB_HIP(hipStreamSynchronize(h->stream));

@@ -137,7 +137,7 @@ struct TubeVariant {
 };
 int num_tube_variants();
 TubeVariant tube_variant(int i);
-hipError_t tube_kernel(int precision, int variant, const void** func, dim3* block);
+hipError_t tube_kernel(int precision, int variant, bool ext, const void** func, dim3* block);
 const char* tube_kernel_name(int precision, int variant);
 
 int num_segment_variants();

@@ -242,9 +242,10 @@ __global__ __launch_bounds__(NT) void k_step_segments(SegLaunch a) {
 // LDS neighbours (a 1 x 1 x L lattice streams only along z: the x and y
 // components of e wrap onto the same cell), barrier, collides in registers,
 // writes them back to its own slot, barrier. Inadmissible counts and
-// diagnostics cover owned cells only (halo cells are computed twice).
+// diagnostics cover owned cells only (halo cells are computed twice). EXT:
+// relaxation times from eta/s and the general equation of state, per cell.
 // -------------------------------------------------------------------------
-template <typename T, int NT>
+template <typename T, int NT, bool EXT>
 __global__ __launch_bounds__(NT) void k_step_tubes(TubeRound a) {
   __shared__ T lds[38][NT];
   const TubeSeg sg = a.segs[blockIdx.x];
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(NT) void k_step_tubes(TubeRound a) {
         a.diag_every > 0 && ((sidx % a.diag_every) == 0 || sidx == a.last_step);
     if (live) {
       Sums s;
-      const bool ok = collide<T>(f, g, d.rt, d.ref, s);
+      const bool ok = collide<T, EXT>(f, g, d.rt, d.ref, s, &d.ext);
       if (owned) {
         nbad += ok ? 0 : 1;
         if (diag)
@@ -500,14 +501,14 @@ const void* seg_func(int v) {
 constexpr TubeVariant kTube[] = {{256, 8}, {256, 16}, {512, 16}, {512, 32}, {128, 8}};
 constexpr int kNumTube = sizeof(kTube) / sizeof(kTube[0]);
 
-template <typename T>
+template <typename T, bool EXT>
 const void* tube_func(int v) {
   switch (v) {
-    case 0: return (const void*)&k_step_tubes<T, 256>;
-    case 1: return (const void*)&k_step_tubes<T, 256>;
-    case 2: return (const void*)&k_step_tubes<T, 512>;
-    case 3: return (const void*)&k_step_tubes<T, 512>;
-    case 4: return (const void*)&k_step_tubes<T, 128>;
+    case 0: return (const void*)&k_step_tubes<T, 256, EXT>;
+    case 1: return (const void*)&k_step_tubes<T, 256, EXT>;
+    case 2: return (const void*)&k_step_tubes<T, 512, EXT>;
+    case 3: return (const void*)&k_step_tubes<T, 512, EXT>;
+    case 4: return (const void*)&k_step_tubes<T, 128, EXT>;
   }
   return nullptr;
 }
@@ -569,9 +570,12 @@ int num_segment_variants() { return kNumSeg; }
 int num_tube_variants() { return kNumTube; }
 TubeVariant tube_variant(int i) { return kTube[i]; }
 
-hipError_t tube_kernel(int precision, int v, const void** func, dim3* block) {
+hipError_t tube_kernel(int precision, int v, bool ext, const void** func, dim3* block) {
   if (v < 0 || v >= kNumTube) return hipErrorInvalidValue;
-  *func = precision ? tube_func<float>(v) : tube_func<double>(v);
+  if (ext)
+    *func = precision ? tube_func<float, true>(v) : tube_func<double, true>(v);
+  else
+    *func = precision ? tube_func<float, false>(v) : tube_func<double, false>(v);
   *block = dim3(kTube[v].nt, 1, 1);
   return hipSuccess;
 }

@@ -79,6 +79,49 @@ def test_massive_shock_tube_400_steps():
     _check(prob, 400, FP64, 1e-11)
 
 
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_massive_tubes_on_tube_rounds(prec):
+    """Two massive-gas tubes (one periodic, one with zero-gradient ends) on
+    every tube-round variant: bit for bit the one-block persistent kernel,
+    which the test above checks against the oracle, and the oracle itself."""
+    import paper_1211_3286_amd as rlb
+    G, m = 1.5, 0.6
+    tubes = []
+    for L, bc in ((700, 1), (333, 0)):
+        t = wl.shock_tube(L, P_L=1.0, n_L=1.0, P_R=0.2, n_R=0.25, tau=0.9)
+        t.params.bc = (0, 0, bc)
+        t.params.eos_gamma, t.params.mass = G, m
+        t.eps = t.eps / 3.0 / (G - 1.0) + m * t.n
+        tubes.append(t)
+    T = 45
+    sim = rlb.from_problems(tubes, precision=prec)
+    names = sim.variants()
+    sim.variant = 0
+    sim.step(T)
+    ref = [x.cpu().numpy() for x in sim.populations()]
+    states, _, bad = gpu_state(sim, tubes)
+    assert bad == 0
+    for p, gs in zip(tubes, states):
+        st = oracle.run(p, T)
+        err = compare(gs, st, st.fields())
+        say("  ", p.name, "prec", prec, err)
+        assert err["f"] < TOL[prec] and err["g"] < TOL[prec], err
+    sim.close()
+    checked = 0
+    for v, name in enumerate(names):
+        if "tubes" not in name:
+            continue
+        s2 = rlb.from_problems(tubes, precision=prec)
+        s2.variant = v
+        s2.step(T)
+        f, g = [x.cpu().numpy() for x in s2.populations()]
+        say("  tube variant", name)
+        assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
+        checked += 1
+        s2.close()
+    assert checked >= 3
+
+
 def test_device_validation_of_the_rest_energy():
     import paper_1211_3286_amd as rlb
     prob = _random(8, 8, 8, (0, 0, 0), "d3q19", m=2.0)  # eps near 1 < m n near 2

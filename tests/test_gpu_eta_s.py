@@ -60,14 +60,15 @@ def test_d2q9_step_matches_oracle(prec, shape):
 @pytest.mark.parametrize("prec,tol", [(FP64, 1e-11), (FP32, 1e-5)])
 def test_sec3_tube_three_tau_f_batch(prec, tol):
     """Sec. III.B: the 1 x 1 x 800 tube at eta/s = 0.1 with tau_f = tau_g,
-    1.0 and 0.6 as one batch, 400 steps (tube rounds are not offered with
-    per-cell relaxation times; the autotuner skips them)."""
+    1.0 and 0.6 as one batch, 400 steps, in the autotuned configuration
+    (segmented launches are not offered with per-cell relaxation times; the
+    autotuner skips them)."""
     import paper_1211_3286_amd as rlb
     tubes = [wl.qgp_tube_3d(0.1, tau_f=tf) for tf in ("tau_g", 1.0, 0.6)]
     sim = rlb.from_problems(tubes, precision=prec)
     res = sim.tune(trial_steps=20)
     say("sec3 batch tuned", res["name"])
-    assert "tubes" not in res["name"] and "segments" not in res["name"]
+    assert "segments" not in res["name"]
     sim.step(400)
     states, sums, bad = gpu_state(sim, tubes)
     assert bad == 0
@@ -100,17 +101,43 @@ def test_corrected_moderate_case_eta_s():
     _check(prob, 400, FP64, 1e-11)
 
 
-def test_tube_rounds_refuse_per_cell_taus():
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-11), (FP32, 1e-5)])
+def test_tube_rounds_with_per_cell_taus(prec, tol):
+    """Tube rounds (LDS windows, H steps a launch) with relaxation times from
+    eta/s: every round variant equals the one-block persistent kernel bit for
+    bit, and the oracle within the tolerance; segmented launches stay refused."""
     import paper_1211_3286_amd as rlb
     tubes = [wl.qgp_tube_3d(0.1, tau_f=0.6, length=L) for L in (300, 500)]
-    sim = rlb.from_problems(tubes, precision=FP32)
+    T = 37
+    sim = rlb.from_problems(tubes, precision=prec)
     names = sim.variants()
+    sim.variant = 0
+    sim.step(T)
+    ref = [t.cpu().numpy() for t in sim.populations()]
+    states, _, bad = gpu_state(sim, tubes)
+    assert bad == 0
+    for p, gs in zip(tubes, states):
+        st = oracle.run(p, T)
+        err = compare(gs, st, st.fields())
+        say("  ", p.name, "prec", prec, err)
+        assert err["f"] < tol and err["g"] < tol and err["u"] < tol, err
+    sim.close()
+    checked = 0
     for v, name in enumerate(names):
-        if "tubes" in name or "segments" in name:
+        if "segments" in name:
+            sim = rlb.from_problems(tubes, precision=prec)
             sim.variant = v
             with pytest.raises(rlb.RLBError) as ei:
                 sim.step(3)
             assert ei.value.code == -7
-    sim.variant = 0
-    sim.step(3)
-    assert np.isfinite(sim.sums()).all()
+            sim.close()
+        elif "tubes" in name:
+            sim = rlb.from_problems(tubes, precision=prec)
+            sim.variant = v
+            sim.step(T)
+            f, g = [t.cpu().numpy() for t in sim.populations()]
+            say("  tube variant", name)
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
+            checked += 1
+            sim.close()
+    assert checked >= 3
