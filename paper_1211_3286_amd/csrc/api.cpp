@@ -127,8 +127,10 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
         parts = std::max(parts, rlb::lattice_partials(v, g));
   }
   parts = std::max<int64_t>(parts, (int64_t)n * rlb::kRefBlocks);
-  if (!lattice_path(n, L.ncells) && !d2) {  // segment tables (D3Q19 persistent path)
-    for (int i = 0; i < n; ++i) L.max_segs += m[i].nz;
+  if (!lattice_path(n, L.ncells)) {  // segment tables of the persistent path
+    // D3Q19: segments of whole z-planes (at most nz per member); D2Q9 strip
+    // rounds: segments of whole rows (at most ny per member)
+    for (int i = 0; i < n; ++i) L.max_segs += d2 ? m[i].ny : m[i].nz;
     parts = std::max<int64_t>(parts, L.max_segs);
   }
   L.max_parts = std::max(parts, 1);
@@ -276,6 +278,12 @@ bool is_tube_variant(const rlb_sim* h, int v) {
 
 int tube_index(int v) { return v - rlb::num_member_variants() - rlb::num_segment_variants(); }
 
+bool is_strip_variant(const rlb_sim* h, int v) {
+  return !h->lattice && h->d2 && v >= rlb::d2q9_num_member_variants();
+}
+
+int strip_index(int v) { return v - rlb::d2q9_num_member_variants(); }
+
 // Tube segments for a tube variant: owned ranges of at most NT - 2H cells,
 // windows extended by H halo cells (cut at zero-gradient ends); a tube that
 // fits the block whole is one segment with exact ends.
@@ -321,21 +329,85 @@ rlb_status build_tube_segments(rlb_sim* h, int tv) {
   return RLB_OK;
 }
 
+// D2Q9 strip segments for a strip variant: windows of R = nt / nx rows, H
+// halo rows a side (2H with the correction term), owned ranges of at most
+// R - 2H rows; a member of at most R rows is one segment with exact ends.
+// RLB_E_UNSUPPORTED when a member is wider than the block or leaves no
+// owned row.
+rlb_status build_strip_segments(rlb_sim* h, int sv) {
+  const rlb::TubeVariant v = rlb::d2q9_strip_variant(sv);
+  const int hr = h->corr ? 2 * v.halo : v.halo;
+  std::vector<rlb::TubeSeg> segs;
+  for (int m = 0; m < h->n_members; ++m) {
+    const MemberDesc& d = h->descs[m];
+    if (d.nx > v.nt) return RLB_E_UNSUPPORTED;
+    const int R = v.nt / d.nx;
+    const int L = d.ny;
+    const bool periodic = d.bcy == RLB_PERIODIC;
+    if (L <= R) {
+      const int kind = periodic ? rlb::kEdgeWrap : rlb::kEdgeClamp;
+      segs.push_back(rlb::TubeSeg{m, 0, L, 0, L, kind, kind});
+      continue;
+    }
+    const int S = R - 2 * hr;
+    if (S < 1) return RLB_E_UNSUPPORTED;
+    const int n = (L + S - 1) / S;
+    for (int j = 0; j < n; ++j) {
+      rlb::TubeSeg g{};
+      g.member = m;
+      g.own0 = (int)((int64_t)L * j / n);
+      g.own1 = (int)((int64_t)L * (j + 1) / n);
+      if (periodic) {
+        g.win0 = g.own0 - hr;
+        g.wlen = g.own1 - g.own0 + 2 * hr;
+        g.left = g.right = rlb::kEdgeHalo;
+      } else {
+        g.win0 = std::max(0, g.own0 - hr);
+        const int win1 = std::min(L, g.own1 + hr);
+        g.wlen = win1 - g.win0;
+        g.left = g.win0 == 0 ? rlb::kEdgeClamp : rlb::kEdgeHalo;
+        g.right = win1 == L ? rlb::kEdgeClamp : rlb::kEdgeHalo;
+      }
+      segs.push_back(g);
+    }
+  }
+  if ((int64_t)segs.size() > h->L.max_segs) return RLB_E_ARG;
+  RLB_HIP(hipMemcpyAsync(h->d_segs, segs.data(), sizeof(rlb::TubeSeg) * segs.size(),
+                         hipMemcpyHostToDevice, h->stream));
+  RLB_HIP(hipStreamSynchronize(h->stream));
+  h->nseg = (int)segs.size();
+  h->seg_built = 2000 + sv;
+  return RLB_OK;
+}
+
 // Tube rounds: ceil(n / H) launches chained in a HIP graph, each round
 // reading one buffer and writing the other (pingpong) or always A -> B
 // (trials). *flip tells whether the state changed buffers.
+// (The D2Q9 strip rounds take the same path with their own segments and
+// kernel.)
 rlb_status launch_tubes(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
                         int diag_every, int64_t step0, bool* flip) {
-  const int tv = tube_index(variant);
-  if (!h->all_tubes) return RLB_E_UNSUPPORTED;
-  if (h->seg_built != 1000 + tv) {
-    rlb_status st = build_tube_segments(h, tv);
-    if (st != RLB_OK) return st;
-  }
-  const rlb::TubeVariant v = rlb::tube_variant(tv);
+  rlb::TubeVariant v;
   const void* func;
   dim3 block;
-  RLB_HIP(rlb::tube_kernel(h->precision, tv, h->ext, &func, &block));
+  if (h->d2) {
+    const int sv = strip_index(variant);
+    if (h->seg_built != 2000 + sv) {
+      rlb_status st = build_strip_segments(h, sv);
+      if (st != RLB_OK) return st;
+    }
+    v = rlb::d2q9_strip_variant(sv);
+    RLB_HIP(rlb::d2q9_strip_kernel(h->precision, sv, h->corr, h->ext, &func, &block));
+  } else {
+    const int tv = tube_index(variant);
+    if (!h->all_tubes) return RLB_E_UNSUPPORTED;
+    if (h->seg_built != 1000 + tv) {
+      rlb_status st = build_tube_segments(h, tv);
+      if (st != RLB_OK) return st;
+    }
+    v = rlb::tube_variant(tv);
+    RLB_HIP(rlb::tube_kernel(h->precision, tv, h->ext, &func, &block));
+  }
   const int rounds = (nsteps + v.halo - 1) / v.halo;
   if (h->tgexec) {  // the previous chain may still run: let it finish first
     RLB_HIP(hipStreamSynchronize(h->stream));
@@ -428,7 +500,7 @@ rlb_status segments_fit(rlb_sim* h, int sv, const void* func, int nt) {
 // again when the kernel changes; later calls only update the arguments).
 rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
                              int diag_every, int64_t step0, bool* flip) {
-  if (is_tube_variant(h, variant))
+  if (is_tube_variant(h, variant) || is_strip_variant(h, variant))
     return launch_tubes(h, variant, nsteps, pingpong, a, b, diag_every, step0, flip);
   *flip = pingpong && (nsteps & 1);
   const void* func;
@@ -533,7 +605,8 @@ rlb_status advance(rlb_sim* h, int32_t n) {
   if (st != RLB_OK) return st;
   if (D > 0) {
     h->diag_step = h->steps + n;
-    const bool by_seg = is_segment_variant(h, h->variant) || is_tube_variant(h, h->variant);
+    const bool by_seg = is_segment_variant(h, h->variant) || is_tube_variant(h, h->variant) ||
+                        is_strip_variant(h, h->variant);
     h->diag_parts = by_seg ? h->nseg : h->n_members;
   }
   h->steps += n;
@@ -586,9 +659,11 @@ bool host_fields_ok(const double* n0, const double* eps0, const double* u0, int6
 namespace {
 
 const char* kernel_name_of(const rlb_sim* h, int v) {
-  if (h->d2)
-    return h->lattice ? rlb::d2q9_lattice_kernel_name(h->precision, v)
-                      : rlb::d2q9_member_kernel_name(h->precision, v);
+  if (h->d2) {
+    if (h->lattice) return rlb::d2q9_lattice_kernel_name(h->precision, v);
+    if (is_strip_variant(h, v)) return rlb::d2q9_strip_kernel_name(h->precision, strip_index(v));
+    return rlb::d2q9_member_kernel_name(h->precision, v);
+  }
   if (h->lattice) return rlb::lattice_kernel_name(h->precision, v);
   if (v < rlb::num_member_variants()) return rlb::member_kernel_name(h->precision, v);
   if (is_segment_variant(h, v))
@@ -940,7 +1015,8 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
 rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
   if (!h || !count) return RLB_E_ARG;
   if (h->d2)
-    *count = h->lattice ? rlb::d2q9_num_lattice_variants() : rlb::d2q9_num_member_variants();
+    *count = h->lattice ? rlb::d2q9_num_lattice_variants()
+                        : rlb::d2q9_num_member_variants() + rlb::d2q9_num_strip_variants();
   else
     *count = h->lattice ? rlb::num_lattice_variants()
                         : rlb::num_member_variants() + rlb::num_segment_variants() +

@@ -235,6 +235,16 @@ __device__ __forceinline__ C7Fields c7_fields(const Macro& m, bool ok) {
   return F;
 }
 
+// Fields of a cell from its pre-collision g (deviations from the reference).
+__device__ __forceinline__ C7Fields c7_fields_of(const double (&gd)[9], const Ref& ref) {
+  const double D1 = gd[1] - gd[3], D2 = gd[2] - gd[4], D5 = gd[5] - gd[7], D6 = gd[6] - gd[8];
+  const double gs =
+      gd[0] + ((gd[1] + gd[3]) + (gd[2] + gd[4])) + ((gd[5] + gd[7]) + (gd[6] + gd[8]));
+  Macro m;
+  const bool ok = recover(3.0 * ref.P + gs, D1 + (D5 - D6), D2 + (D5 + D6), 0.0, m);
+  return c7_fields(m, ok);
+}
+
 // Fields of the cell whose pull offsets are off (its pre-collision g).
 template <typename T>
 __device__ __forceinline__ C7Fields c7_fields_at(const T* __restrict__ src, int64_t cs,
@@ -242,12 +252,7 @@ __device__ __forceinline__ C7Fields c7_fields_at(const T* __restrict__ src, int6
   double gd[9];
 #pragma unroll
   for (int a = 0; a < 9; ++a) gd[a] = (double)ld(src + (int64_t)(9 + a) * cs, off[a]);
-  const double D1 = gd[1] - gd[3], D2 = gd[2] - gd[4], D5 = gd[5] - gd[7], D6 = gd[6] - gd[8];
-  const double gs =
-      gd[0] + ((gd[1] + gd[3]) + (gd[2] + gd[4])) + ((gd[5] + gd[7]) + (gd[6] + gd[8]));
-  Macro m;
-  const bool ok = recover(3.0 * ref.P + gs, D1 + (D5 - D6), D2 + (D5 + D6), 0.0, m);
-  return c7_fields(m, ok);
+  return c7_fields_of(gd, ref);
 }
 
 // Row-7 correction of a cell from its own recovery and its y-neighbours.

@@ -170,6 +170,13 @@ int d2q9_num_member_variants();
 hipError_t d2q9_member_kernel(int precision, int variant, bool corr, bool ext, const void** func,
                               dim3* block);
 const char* d2q9_member_kernel_name(int precision, int variant);
+// Strip rounds (k_d2q9_strips): TubeVariant.halo is the number of steps per
+// launch; the window's halo is that many rows, twice that with the correction.
+int d2q9_num_strip_variants();
+TubeVariant d2q9_strip_variant(int i);
+hipError_t d2q9_strip_kernel(int precision, int variant, bool corr, bool ext, const void** func,
+                             dim3* block);
+const char* d2q9_strip_kernel_name(int precision, int variant);
 hipError_t d2q9_launch_init(int precision, void* state, int64_t cs, const MemberDesc* descs,
                             int n_members, const double* n0, const double* eps0,
                             const double* u0, int64_t ncells, hipStream_t s);

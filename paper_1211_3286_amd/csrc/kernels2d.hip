@@ -148,6 +148,127 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
   if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
 }
 
+// -------------------------------------------------------------------------
+// Strip rounds over a batch of members narrow in x and long in y (the
+// 4 x 800 tubes of Sec. V.B): every member is cut into segments of whole
+// rows, and one block holds a segment's window (owned rows plus halo rows on
+// each side, all nx columns) in LDS as [18][NT], one thread per window cell
+// (w = row * nx + x). Each launch advances nsteps <= H steps there; halo
+// rows absorb the error of the unknown rows beyond the window, which moves
+// one row per step (two with the correction term, whose y-neighbour fields
+// come from cells one row further out). Per step: pull the 18 values from
+// the LDS neighbours (x by the member's rule; y inside the window, wrapped
+// only when the window is a whole periodic member, else held at the window
+// edge, which is exact at a zero-gradient end), publish the cell's C_7
+// fields (CORR), barrier, collide, write back in place, barrier. Cells,
+// counts and diagnostics of owned rows only are kept; the arithmetic is that
+// of k_d2q9_members, so results are identical bit for bit.
+// -------------------------------------------------------------------------
+template <typename T, int NT, bool CORR, bool EXT>
+__global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
+  __shared__ T lds[18][NT];
+  __shared__ double cf[CORR ? 4 : 1][CORR ? NT : 1];  // x1, gamma, sigma u^2, sigma u
+  __shared__ int cok[CORR ? NT : 1];
+  const TubeSeg sg = a.segs[blockIdx.x];
+  const MemberDesc d = a.descs[sg.member];
+  const int nx = d.nx;
+  const int w = threadIdx.x;
+  const bool live = w < sg.wlen * nx;
+  const int r = live ? w / nx : 0;  // window row
+  const int x = live ? w - r * nx : 0;
+  const bool owned = live && r >= sg.own0 - sg.win0 && r < sg.own1 - sg.win0;
+  int y = sg.win0 + r;
+  if (y < 0) y += d.ny;
+  if (y >= d.ny) y -= d.ny;
+  const int64_t gi = d.offset + (int64_t)y * nx + x;
+  if (live) {
+#pragma unroll
+    for (int p = 0; p < 18; ++p) lds[p][w] = ((const T*)a.src)[p * a.cs + gi];
+  }
+  // window rows of the y - 1 and y + 1 neighbours, columns of x - 1 and x + 1
+  int rm = r - 1, rp = r + 1;
+  if (rm < 0) rm = sg.left == kEdgeWrap ? sg.wlen - 1 : 0;
+  if (rp >= sg.wlen) rp = sg.right == kEdgeWrap ? 0 : sg.wlen - 1;
+  const int xm = nbr(x, -1, nx, d.bcx), xp = nbr(x, 1, nx, d.bcx);
+  int slot[9];  // pull source of velocity a: the cell at (x, y) - e_a
+  slot[0] = r * nx + x;
+  slot[1] = r * nx + xm;
+  slot[2] = rm * nx + x;
+  slot[3] = r * nx + xp;
+  slot[4] = rp * nx + x;
+  slot[5] = rm * nx + xm;
+  slot[6] = rm * nx + xp;
+  slot[7] = rp * nx + xp;
+  slot[8] = rp * nx + xm;
+  if (!live)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) slot[q] = 0;
+  const int sm = rm * nx + x, sp = rp * nx + x;  // C_7 neighbours
+  __syncthreads();
+  int nbad = 0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < a.nsteps; ++t) {
+    T f[9], g[9];
+    if (live) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        f[q] = lds[q][slot[q]];
+        g[q] = lds[9 + q][slot[q]];
+      }
+      if constexpr (CORR) {
+        double gd[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) gd[q] = (double)g[q];
+        const d2q9::C7Fields F = d2q9::c7_fields_of(gd, d.ref);
+        cf[0][w] = F.x1;
+        cf[1][w] = F.gam;
+        cf[2][w] = F.su2;
+        cf[3][w] = F.su;
+        cok[w] = F.ok ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag =
+        a.diag_every > 0 && ((sidx % a.diag_every) == 0 || sidx == a.last_step);
+    if (live) {
+      d2q9::C7Fields fm, fp;
+      if constexpr (CORR) {
+        fm = d2q9::C7Fields{cf[0][sm], cf[1][sm], cf[2][sm], cf[3][sm], cok[sm] != 0};
+        fp = d2q9::C7Fields{cf[0][sp], cf[1][sp], cf[2][sp], cf[3][sp], cok[sp] != 0};
+      }
+      Sums s;
+      const bool ok = d2q9::collide<T, CORR, EXT>(f, g, d.rt, d.ref, s, &fm, &fp, &d.ext);
+      if (owned) {
+        nbad += ok ? 0 : 1;
+        if (diag)
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] = s.v[i];
+      }
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        lds[q][w] = f[q];
+        lds[9 + q][w] = g[q];
+      }
+    }
+    if (diag) {
+      if (!owned)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) acc[i] = 0.0;
+      block_sum5<NT>(acc, w);
+      if (w == 0)
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a.partials[(int64_t)blockIdx.x * 5 + i] = acc[i];
+    }
+    __syncthreads();
+  }
+  if (owned) {
+#pragma unroll
+    for (int p = 0; p < 18; ++p) ((T*)a.dst)[p * a.cs + gi] = lds[p][w];
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
 __device__ __forceinline__ int member_of(const MemberDesc* __restrict__ d, int n, int64_t c) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -246,6 +367,9 @@ constexpr LatticeVariant kLat2[] = {{64, 1, 1},  {128, 1, 1}, {256, 1, 1}, {64, 
 constexpr int kNumLat2 = sizeof(kLat2) / sizeof(kLat2[0]);
 constexpr MemberVariant kMem2[] = {{256, 1}, {512, 1}, {1024, 1}, {512, 2}, {1024, 2}};
 constexpr int kNumMem2 = sizeof(kMem2) / sizeof(kMem2[0]);
+// strip rounds: threads per block, steps per launch
+constexpr TubeVariant kStrip2[] = {{128, 2}, {128, 4}, {256, 4}, {256, 8}, {512, 8}, {512, 16}};
+constexpr int kNumStrip2 = sizeof(kStrip2) / sizeof(kStrip2[0]);
 
 int grid2_for(int64_t n) {
   int64_t b = (n + 255) / 256;
@@ -292,6 +416,19 @@ const void* mem2_func(int v) {
     case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR, EXT>;
     case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR, EXT>;
     case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR, EXT>;
+  }
+  return nullptr;
+}
+
+template <typename T, bool CORR, bool EXT>
+const void* strip2_func(int v) {
+  switch (v) {
+    case 0: return (const void*)&k_d2q9_strips<T, 128, CORR, EXT>;
+    case 1: return (const void*)&k_d2q9_strips<T, 128, CORR, EXT>;
+    case 2: return (const void*)&k_d2q9_strips<T, 256, CORR, EXT>;
+    case 3: return (const void*)&k_d2q9_strips<T, 256, CORR, EXT>;
+    case 4: return (const void*)&k_d2q9_strips<T, 512, CORR, EXT>;
+    case 5: return (const void*)&k_d2q9_strips<T, 512, CORR, EXT>;
   }
   return nullptr;
 }
@@ -361,6 +498,34 @@ const char* d2q9_member_kernel_name(int precision, int v) {
                               "k_d2q9_members<double,1024,1>", "k_d2q9_members<double,512,2>",
                               "k_d2q9_members<double,1024,2>"};
   if (v < 0 || v >= kNumMem2) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+int d2q9_num_strip_variants() { return kNumStrip2; }
+TubeVariant d2q9_strip_variant(int i) { return kStrip2[i]; }
+
+template <typename T>
+const void* strip2_modes(int v, bool corr, bool ext) {
+  if (corr) return ext ? strip2_func<T, true, true>(v) : strip2_func<T, true, false>(v);
+  return ext ? strip2_func<T, false, true>(v) : strip2_func<T, false, false>(v);
+}
+
+hipError_t d2q9_strip_kernel(int precision, int v, bool corr, bool ext, const void** func,
+                             dim3* block) {
+  if (v < 0 || v >= kNumStrip2) return hipErrorInvalidValue;
+  *func = precision ? strip2_modes<float>(v, corr, ext) : strip2_modes<double>(v, corr, ext);
+  *block = dim3(kStrip2[v].nt, 1, 1);
+  return hipSuccess;
+}
+
+const char* d2q9_strip_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_d2q9_strips<float,128>/h2", "k_d2q9_strips<float,128>/h4",
+                              "k_d2q9_strips<float,256>/h4", "k_d2q9_strips<float,256>/h8",
+                              "k_d2q9_strips<float,512>/h8", "k_d2q9_strips<float,512>/h16"};
+  static const char* n64[] = {"k_d2q9_strips<double,128>/h2", "k_d2q9_strips<double,128>/h4",
+                              "k_d2q9_strips<double,256>/h4", "k_d2q9_strips<double,256>/h8",
+                              "k_d2q9_strips<double,512>/h8", "k_d2q9_strips<double,512>/h16"};
+  if (v < 0 || v >= kNumStrip2) return "?";
   return precision ? n32[v] : n64[v];
 }
 
