@@ -326,6 +326,66 @@ def cpu_baseline(prob, seconds: float):
     return rec, st, n + 1
 
 
+def cpu_baseline_sweep(seconds: float = 4.0) -> dict:
+    """The CPU baseline on every benchmark configuration: the FP64 oracle
+    (as it stands) timed on all host cores and on one core, in cell updates
+    per second (the adjoint: cell-steps of the gradient per second). Each
+    figure is a bounded sample of about ``seconds`` of work after one untimed
+    step. Context for the GPU figures, not a target."""
+    import numpy as np
+    import oracle
+    import workloads as wl
+    cores = oracle.max_threads()
+
+    def timed(run, cells):
+        t0 = time.perf_counter()
+        run(1)
+        one = time.perf_counter() - t0
+        n = max(1, int(seconds / max(one, 1e-9)))
+        t0 = time.perf_counter()
+        run(n)
+        dt = time.perf_counter() - t0
+        return {"mlups": cells * n / dt / 1e6, "steps": n, "seconds": round(dt, 2)}
+
+    def forward(probs):
+        def go(threads):
+            oracle.set_threads(threads)
+            states = [oracle.State.init(p) for p in probs]
+
+            def run(n):
+                for st in states:
+                    st.step(n)
+            return timed(run, sum(p.params.ncells for p in probs))
+        return go
+
+    def adjoint(prob):
+        sh = prob.params.shape
+        rng = np.random.default_rng(1)
+        du, de = rng.standard_normal((3,) + sh), rng.standard_normal(sh)
+
+        def go(threads):
+            oracle.set_threads(threads)
+            return timed(lambda n: oracle.grad(prob, n, du, de), prob.params.ncells)
+        return go
+
+    configs = {
+        "shock_tube_1x1x800": forward([wl.shock_tube(800)]),
+        "random_modes_256x256x256": forward([wl.random_modes(
+            256, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55, tau_eps=0.7, tau_f=0.8)]),
+        "tube_batch_64": forward(wl.tube_batch()),
+        "adjoint_shear_vortex_64x64": adjoint(wl.shear_vortex(64)),
+        "blast_128x128x128": forward([wl.blast(128)]),
+    }
+    out = {"kind": "oracle", "cores": cores, "unit": "MLUPS"}
+    try:
+        for name, go in configs.items():
+            out[name] = {"all_cores": go(cores), "one_core": go(1)}
+            log("oracle sweep", name, out[name])
+    finally:
+        oracle.set_threads(cores)
+    return out
+
+
 def error_vs_oracle(torch, rlb, prob, st, steps: int, kernels, diag_every: int):
     """Max-norm errors of the GPU path against the oracle state of the CPU
     baseline (the same input, the same number of steps), over every cell:
@@ -447,6 +507,9 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--oracle-sweep", action="store_true",
+                    help="time the CPU oracle on every configuration (all cores and one "
+                         "core), print one JSON line and exit")
     ap.add_argument("--no-forms", action="store_true", help="only the headline FP32 step")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--diag-every", type=int, default=50,
@@ -460,6 +523,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.oracle_sweep:
+        print(json.dumps(cpu_baseline_sweep()), flush=True)
         return
     if args.write_traffic:
         rec = write_traffic(*args.write_traffic)
