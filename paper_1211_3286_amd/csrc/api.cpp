@@ -85,6 +85,20 @@ bool lattice_path(int32_t n_members, int64_t ncells) {
 // Velocities per distribution of a lattice kind.
 int nvel(int32_t lattice) { return lattice == RLB_D2Q9 ? 9 : 19; }
 
+// Tile geometry of a D2Q9 tile variant on an nx x ny lattice: halo cells a
+// side (y doubled with the correction term), owned cells per tile and the
+// grid. false when a tiled axis leaves no owned cell.
+bool tile_geometry(const rlb::TileVariant& v, int nx, int ny, bool corr, rlb::TileRound& a,
+                   dim3& grid) {
+  a.hx = v.h;
+  a.hy = corr ? 2 * v.h : v.h;
+  a.ox = v.tx - 2 * a.hx;
+  a.oy = v.ty - 2 * a.hy;
+  if ((nx > v.tx && a.ox < 1) || (ny > v.ty && a.oy < 1)) return false;
+  grid = dim3(nx <= v.tx ? 1 : (nx + a.ox - 1) / a.ox, ny <= v.ty ? 1 : (ny + a.oy - 1) / a.oy, 1);
+  return true;
+}
+
 rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, Layout& L) {
   if (!opt) return RLB_E_ARG;
   if (opt->precision != RLB_FP32 && opt->precision != RLB_FP64) return RLB_E_ARG;
@@ -119,9 +133,16 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
     g.nx = m[0].nx;
     g.ny = m[0].ny;
     g.nz = m[0].nz;
-    if (d2)
+    if (d2) {
       for (int v = 0; v < rlb::d2q9_num_lattice_variants(); ++v)
         parts = std::max(parts, rlb::d2q9_lattice_partials(v, g));
+      for (int v = 0; v < rlb::d2q9_num_tile_variants(); ++v) {
+        rlb::TileRound a{};
+        dim3 grid;
+        if (tile_geometry(rlb::d2q9_tile_variant(v), g.nx, g.ny, opt->correction != 0, a, grid))
+          parts = std::max<int64_t>(parts, (int64_t)grid.x * grid.y);
+      }
+    }
     else
       for (int v = 0; v < rlb::num_lattice_variants(); ++v)
         parts = std::max(parts, rlb::lattice_partials(v, g));
@@ -259,9 +280,59 @@ rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* s
                                           h->d_partials, h->d_bad, h->stream));
 }
 
+bool is_tile_variant(const rlb_sim* h, int v) {
+  return h->lattice && h->d2 && v >= rlb::d2q9_num_lattice_variants();
+}
+
+int tile_index(int v) { return v - rlb::d2q9_num_lattice_variants(); }
+
 int lattice_parts(const rlb_sim* h, int variant) {
+  if (is_tile_variant(h, variant)) {
+    rlb::TileRound a{};
+    dim3 grid;
+    tile_geometry(rlb::d2q9_tile_variant(tile_index(variant)), h->geom.nx, h->geom.ny, h->corr,
+                  a, grid);
+    return (int)(grid.x * grid.y);
+  }
   return h->d2 ? rlb::d2q9_lattice_partials(variant, h->geom)
                : rlb::lattice_partials(variant, h->geom);
+}
+
+// D2Q9 tile rounds: ceil(n / H) launches, each advancing up to H steps of the
+// whole lattice; rounds alternate the buffers (pingpong) or always read a and
+// write b (trials). *flip tells whether the state changed buffers.
+rlb_status launch_tile_rounds(rlb_sim* h, int variant, int nsteps, int pingpong, void* a, void* b,
+                              int diag_every, int64_t step0, bool* flip) {
+  const rlb::TileVariant v = rlb::d2q9_tile_variant(tile_index(variant));
+  rlb::TileRound arg{};
+  dim3 grid;
+  if (!rlb::d2q9_tile_fits(h->precision, tile_index(variant), h->corr) ||
+      !tile_geometry(v, h->geom.nx, h->geom.ny, h->corr, arg, grid))
+    return RLB_E_UNSUPPORTED;
+  arg.cs = h->L.cs;
+  arg.nx = h->geom.nx;
+  arg.ny = h->geom.ny;
+  arg.bcx = h->geom.bcx;
+  arg.bcy = h->geom.bcy;
+  arg.diag_every = diag_every;
+  arg.last_step = step0 + nsteps;
+  arg.rt = h->geom.rt;
+  arg.ref = h->geom.ref;
+  arg.ext = h->geom.ext;
+  arg.partials = h->d_partials;
+  arg.bad = h->d_bad;
+  const int rounds = (nsteps + v.h - 1) / v.h;
+  for (int r = 0; r < rounds; ++r) {
+    const bool odd = pingpong && (r & 1);
+    arg.src = odd ? b : a;
+    arg.dst = odd ? a : b;
+    arg.nsteps = std::min(v.h, nsteps - r * v.h);
+    arg.step0 = step0 + (int64_t)r * v.h;
+    RLB_HIP(rlb::d2q9_launch_tiles(h->precision, tile_index(variant), h->corr, h->ext, arg, grid,
+                                   h->stream));
+  }
+  *flip = pingpong && (rounds & 1);
+  return RLB_OK;
 }
 
 constexpr int kSpinLimit = 1 << 24;  // about a second of polling per wait
@@ -584,6 +655,19 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
 rlb_status advance(rlb_sim* h, int32_t n) {
   if (n <= 0) return RLB_OK;
   const int D = h->opt.diag_every;
+  if (h->lattice && is_tile_variant(h, h->variant)) {
+    bool flip = false;
+    rlb_status st =
+        launch_tile_rounds(h, h->variant, n, 1, state_buf(h), spare_buf(h), D, h->steps, &flip);
+    if (st != RLB_OK) return st;
+    if (D > 0) {
+      h->diag_step = h->steps + n;
+      h->diag_parts = lattice_parts(h, h->variant);
+    }
+    h->steps += n;
+    if (flip) h->cur = 1 - h->cur;
+    return RLB_OK;
+  }
   if (h->lattice) {
     for (int32_t i = 0; i < n; ++i) {
       const int64_t s = h->steps + 1;
@@ -660,6 +744,7 @@ namespace {
 
 const char* kernel_name_of(const rlb_sim* h, int v) {
   if (h->d2) {
+    if (is_tile_variant(h, v)) return rlb::d2q9_tile_kernel_name(h->precision, tile_index(v));
     if (h->lattice) return rlb::d2q9_lattice_kernel_name(h->precision, v);
     if (is_strip_variant(h, v)) return rlb::d2q9_strip_kernel_name(h->precision, strip_index(v));
     return rlb::d2q9_member_kernel_name(h->precision, v);
@@ -1015,7 +1100,7 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
 rlb_status rlb_num_variants(rlb_handle h, int32_t* count) {
   if (!h || !count) return RLB_E_ARG;
   if (h->d2)
-    *count = h->lattice ? rlb::d2q9_num_lattice_variants()
+    *count = h->lattice ? rlb::d2q9_num_lattice_variants() + rlb::d2q9_num_tile_variants()
                         : rlb::d2q9_num_member_variants() + rlb::d2q9_num_strip_variants();
   else
     *count = h->lattice ? rlb::num_lattice_variants()
@@ -1068,7 +1153,14 @@ rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
     bool usable = true;
     for (int rep = 0; rep < 2 && st == RLB_OK && usable; ++rep) {  // rep 0 warms up
       if (hipEventRecord(e0, h->stream) != hipSuccess) st = RLB_E_DEVICE;
-      if (h->lattice) {
+      if (h->lattice && is_tile_variant(h, v)) {
+        bool flip = false;
+        st = launch_tile_rounds(h, v, trial_steps, 0, state_buf(h), spare_buf(h), 0, 0, &flip);
+        if (st == RLB_E_UNSUPPORTED) {  // a tiled axis leaves no owned cell
+          usable = false;
+          st = RLB_OK;
+        }
+      } else if (h->lattice) {
         for (int i = 0; i < trial_steps && st == RLB_OK; ++i)
           st = launch_lattice_step(h, v, false, state_buf(h), spare_buf(h));
       } else if (st == RLB_OK) {

@@ -170,6 +170,34 @@ int d2q9_num_member_variants();
 hipError_t d2q9_member_kernel(int precision, int variant, bool corr, bool ext, const void** func,
                               dim3* block);
 const char* d2q9_member_kernel_name(int precision, int variant);
+// Tile rounds of the D2Q9 lattice path (k_d2q9_tiles): one block per tile of
+// ox x oy owned cells, whose window (the tile plus hx / hy halo cells a side,
+// cut at zero-gradient faces; an axis no longer than the block is taken whole)
+// advances nsteps <= H steps in LDS.
+struct TileRound {
+  const void* src;
+  void* dst;
+  int64_t cs;
+  int32_t nx, ny, bcx, bcy;
+  int32_t ox, oy;  // owned cells per tile and axis (when the axis is tiled)
+  int32_t hx, hy;  // halo cells a side per axis
+  int32_t nsteps, diag_every;
+  int64_t step0, last_step;
+  Rates rt;
+  Ref ref;
+  Ext ext;
+  double* partials;
+  unsigned long long* bad;
+};
+struct TileVariant {
+  int tx, ty, h;  // block (= window) shape, steps per launch
+};
+int d2q9_num_tile_variants();
+bool d2q9_tile_fits(int precision, int variant, bool corr);  // LDS of the block within 160 KB
+TileVariant d2q9_tile_variant(int i);
+hipError_t d2q9_launch_tiles(int precision, int variant, bool corr, bool ext, const TileRound& a,
+                             dim3 grid, hipStream_t s);
+const char* d2q9_tile_kernel_name(int precision, int variant);
 // Strip rounds (k_d2q9_strips): TubeVariant.halo is the number of steps per
 // launch; the window's halo is that many rows, twice that with the correction.
 int d2q9_num_strip_variants();

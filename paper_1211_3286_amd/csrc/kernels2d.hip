@@ -269,6 +269,188 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
   if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
 }
 
+// -------------------------------------------------------------------------
+// Tile rounds on one D2Q9 lattice (temporal blocking): a block of NTH threads
+// holds the TX x TY window of its tile (the owned cells plus hx / hy halo
+// cells a side) in LDS as [18][TX*TY], each thread TX*TY/NTH window cells
+// (c = tid + k NTH, i = c mod TX, j = c / TX), and advances nsteps <= H
+// steps there before writing the owned cells. Each round reads every window
+// cell once and writes every owned cell once, so HBM traffic per cell update
+// falls from 2 x 18 values to about (1 + window/owned) x 18 / H. Windows are
+// cut at zero-gradient faces (pulls held at the window edge there are exact);
+// an axis no longer than the block is one whole window, wrapped if periodic.
+// The step itself is that of k_d2q9_strips (pull from LDS, C_7 fields
+// published in LDS, collide in registers, write back in place), and gives the
+// same results as the one-step kernels bit for bit.
+// -------------------------------------------------------------------------
+struct AxisWindow {
+  int w0, wlen, own0, own1;  // window start (may be < 0 when periodic), length, owned range
+  int left, right;           // edge kinds
+};
+
+__device__ __forceinline__ AxisWindow axis_window(int b, int N, int T, int O, int h, int bc) {
+  AxisWindow w;
+  if (N <= T) {  // the whole axis
+    w.w0 = 0;
+    w.wlen = N;
+    w.own0 = 0;
+    w.own1 = N;
+    w.left = w.right = bc == 0 ? kEdgeWrap : kEdgeClamp;
+    return w;
+  }
+  w.own0 = b * O;
+  w.own1 = min(N, w.own0 + O);
+  if (bc == 0) {
+    w.w0 = w.own0 - h;
+    w.wlen = w.own1 - w.own0 + 2 * h;
+    w.left = w.right = kEdgeHalo;
+  } else {
+    w.w0 = max(0, w.own0 - h);
+    const int w1 = min(N, w.own1 + h);
+    w.wlen = w1 - w.w0;
+    w.left = w.w0 == 0 ? kEdgeClamp : kEdgeHalo;
+    w.right = w1 == N ? kEdgeClamp : kEdgeHalo;
+  }
+  return w;
+}
+
+template <typename T, int TX, int TY, int NTH, bool CORR, bool EXT>
+__global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
+  constexpr int NT = TX * TY;     // window cells
+  constexpr int CPT = NT / NTH;   // window cells per thread: c = tid + k * NTH
+  static_assert(CPT * NTH == NT, "threads must divide the window");
+  __shared__ T lds[18][NT];
+  __shared__ double cf[CORR ? 4 : 1][CORR ? NT : 1];  // x1, gamma, sigma u^2, sigma u
+  __shared__ int cok[CORR ? NT : 1];
+  const AxisWindow X = axis_window(blockIdx.x, a.nx, TX, a.ox, a.hx, a.bcx);
+  const AxisWindow Y = axis_window(blockIdx.y, a.ny, TY, a.oy, a.hy, a.bcy);
+  const int tid = threadIdx.x;
+  bool live[CPT], owned[CPT];
+  int64_t gi[CPT];
+  int slot[CPT][9], sm[CPT], sp[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = tid + k * NTH;
+    const int i = c % TX, j = c / TX;
+    live[k] = i < X.wlen && j < Y.wlen;
+    owned[k] = live[k] && X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
+               Y.w0 + j < Y.own1;
+    int gx = X.w0 + i, gy = Y.w0 + j;
+    if (gx < 0) gx += a.nx;
+    if (gx >= a.nx) gx -= a.nx;
+    if (gy < 0) gy += a.ny;
+    if (gy >= a.ny) gy -= a.ny;
+    gi[k] = (int64_t)gy * a.nx + gx;
+    if (live[k]) {
+#pragma unroll
+      for (int p = 0; p < 18; ++p) lds[p][c] = ((const T*)a.src)[p * a.cs + gi[k]];
+    }
+    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+    if (im < 0) im = X.left == kEdgeWrap ? X.wlen - 1 : 0;
+    if (ip >= X.wlen) ip = X.right == kEdgeWrap ? 0 : X.wlen - 1;
+    if (jm < 0) jm = Y.left == kEdgeWrap ? Y.wlen - 1 : 0;
+    if (jp >= Y.wlen) jp = Y.right == kEdgeWrap ? 0 : Y.wlen - 1;
+    // pull source of velocity a: the cell at (i, j) - e_a
+    slot[k][0] = j * TX + i;
+    slot[k][1] = j * TX + im;
+    slot[k][2] = jm * TX + i;
+    slot[k][3] = j * TX + ip;
+    slot[k][4] = jp * TX + i;
+    slot[k][5] = jm * TX + im;
+    slot[k][6] = jm * TX + ip;
+    slot[k][7] = jp * TX + ip;
+    slot[k][8] = jp * TX + im;
+    sm[k] = jm * TX + i;  // C_7 neighbours
+    sp[k] = jp * TX + i;
+    if (!live[k]) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) slot[k][q] = 0;
+      sm[k] = sp[k] = 0;
+    }
+  }
+  __syncthreads();
+  int nbad = 0;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < a.nsteps; ++t) {
+    // every pull of the step lands in registers before the in-place writes
+    T f[CPT][9], g[CPT][9];
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (live[k]) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          f[k][q] = lds[q][slot[k][q]];
+          g[k][q] = lds[9 + q][slot[k][q]];
+        }
+        if constexpr (CORR) {
+          double gd[9];
+#pragma unroll
+          for (int q = 0; q < 9; ++q) gd[q] = (double)g[k][q];
+          const d2q9::C7Fields F = d2q9::c7_fields_of(gd, a.ref);
+          const int c = tid + k * NTH;
+          cf[0][c] = F.x1;
+          cf[1][c] = F.gam;
+          cf[2][c] = F.su2;
+          cf[3][c] = F.su;
+          cok[c] = F.ok ? 1 : 0;
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t sidx = a.step0 + t + 1;
+    const bool diag =
+        a.diag_every > 0 && ((sidx % a.diag_every) == 0 || sidx == a.last_step);
+    if (diag)
+#pragma unroll
+      for (int q = 0; q < 5; ++q) acc[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (live[k]) {
+        d2q9::C7Fields fm, fp;
+        if constexpr (CORR) {
+          const int m = sm[k], p = sp[k];
+          fm = d2q9::C7Fields{cf[0][m], cf[1][m], cf[2][m], cf[3][m], cok[m] != 0};
+          fp = d2q9::C7Fields{cf[0][p], cf[1][p], cf[2][p], cf[3][p], cok[p] != 0};
+        }
+        Sums s;
+        const bool ok =
+            d2q9::collide<T, CORR, EXT>(f[k], g[k], a.rt, a.ref, s, &fm, &fp, &a.ext);
+        if (owned[k]) {
+          nbad += ok ? 0 : 1;
+          if (diag)
+#pragma unroll
+            for (int q = 0; q < 5; ++q) acc[q] += s.v[q];
+        }
+        const int c = tid + k * NTH;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          lds[q][c] = f[k][q];
+          lds[9 + q][c] = g[k][q];
+        }
+      }
+    }
+    if (diag) {
+      block_sum5<NTH>(acc, tid);
+      if (tid == 0) {
+        const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) a.partials[b * 5 + q] = acc[q];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    if (owned[k]) {
+      const int c = tid + k * NTH;
+#pragma unroll
+      for (int p = 0; p < 18; ++p)
+        st_nt((T*)a.dst + (int64_t)p * a.cs, (uint32_t)(gi[k] * sizeof(T)), lds[p][c]);
+    }
+  }
+  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+}
+
 __device__ __forceinline__ int member_of(const MemberDesc* __restrict__ d, int n, int64_t c) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -420,6 +602,44 @@ const void* mem2_func(int v) {
   return nullptr;
 }
 
+// tile rounds: block (= window) shape and steps per launch
+constexpr TileVariant kTile2[] = {{32, 16, 2}, {64, 8, 2}, {32, 32, 2}, {64, 16, 2}, {32, 32, 3},
+                                  {64, 16, 3}};
+constexpr int kNumTile2 = sizeof(kTile2) / sizeof(kTile2[0]);
+
+// LDS of a tile block: the window's 18 populations, and with the correction
+// term its published fields (4 doubles and a flag per cell).
+constexpr size_t tile_lds_bytes(size_t esz, int nt, bool corr) {
+  return 18 * (size_t)nt * esz + (corr ? (size_t)nt * (4 * sizeof(double) + sizeof(int)) : 0);
+}
+constexpr size_t kLdsLimit = 160 * 1024;
+
+constexpr int kTileThreads = 512;
+
+template <typename T, int TX, int TY, bool CORR, bool EXT>
+hipError_t tile2_launch(const TileRound& a, dim3 grid, hipStream_t s) {
+  if constexpr (tile_lds_bytes(sizeof(T), TX * TY, CORR) > kLdsLimit) {
+    return hipErrorInvalidValue;  // refused on the host (d2q9_tile_fits)
+  } else {
+    hipLaunchKernelGGL((k_d2q9_tiles<T, TX, TY, kTileThreads, CORR, EXT>), grid,
+                       dim3(kTileThreads, 1, 1), 0, s, a);
+    return hipGetLastError();
+  }
+}
+
+template <typename T, bool CORR, bool EXT>
+hipError_t tile2_dispatch(int v, const TileRound& a, dim3 grid, hipStream_t s) {
+  switch (v) {
+    case 0: return tile2_launch<T, 32, 16, CORR, EXT>(a, grid, s);
+    case 1: return tile2_launch<T, 64, 8, CORR, EXT>(a, grid, s);
+    case 2: return tile2_launch<T, 32, 32, CORR, EXT>(a, grid, s);
+    case 3: return tile2_launch<T, 64, 16, CORR, EXT>(a, grid, s);
+    case 4: return tile2_launch<T, 32, 32, CORR, EXT>(a, grid, s);
+    case 5: return tile2_launch<T, 64, 16, CORR, EXT>(a, grid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename T, bool CORR, bool EXT>
 const void* strip2_func(int v) {
   switch (v) {
@@ -498,6 +718,39 @@ const char* d2q9_member_kernel_name(int precision, int v) {
                               "k_d2q9_members<double,1024,1>", "k_d2q9_members<double,512,2>",
                               "k_d2q9_members<double,1024,2>"};
   if (v < 0 || v >= kNumMem2) return "?";
+  return precision ? n32[v] : n64[v];
+}
+
+int d2q9_num_tile_variants() { return kNumTile2; }
+bool d2q9_tile_fits(int precision, int v, bool corr) {
+  return tile_lds_bytes(precision ? 4 : 8, kTile2[v].tx * kTile2[v].ty, corr) <= kLdsLimit;
+}
+TileVariant d2q9_tile_variant(int i) { return kTile2[i]; }
+
+template <typename T>
+hipError_t tile2_modes(int v, bool corr, bool ext, const TileRound& a, dim3 grid, hipStream_t s) {
+  if (corr)
+    return ext ? tile2_dispatch<T, true, true>(v, a, grid, s)
+               : tile2_dispatch<T, true, false>(v, a, grid, s);
+  return ext ? tile2_dispatch<T, false, true>(v, a, grid, s)
+             : tile2_dispatch<T, false, false>(v, a, grid, s);
+}
+
+hipError_t d2q9_launch_tiles(int precision, int v, bool corr, bool ext, const TileRound& a,
+                             dim3 grid, hipStream_t s) {
+  if (v < 0 || v >= kNumTile2) return hipErrorInvalidValue;
+  return precision ? tile2_modes<float>(v, corr, ext, a, grid, s)
+                   : tile2_modes<double>(v, corr, ext, a, grid, s);
+}
+
+const char* d2q9_tile_kernel_name(int precision, int v) {
+  static const char* n32[] = {"k_d2q9_tiles<float,32,16>/h2", "k_d2q9_tiles<float,64,8>/h2",
+                              "k_d2q9_tiles<float,32,32>/h2", "k_d2q9_tiles<float,64,16>/h2",
+                              "k_d2q9_tiles<float,32,32>/h3", "k_d2q9_tiles<float,64,16>/h3"};
+  static const char* n64[] = {"k_d2q9_tiles<double,32,16>/h2", "k_d2q9_tiles<double,64,8>/h2",
+                              "k_d2q9_tiles<double,32,32>/h2", "k_d2q9_tiles<double,64,16>/h2",
+                              "k_d2q9_tiles<double,32,32>/h3", "k_d2q9_tiles<double,64,16>/h3"};
+  if (v < 0 || v >= kNumTile2) return "?";
   return precision ? n32[v] : n64[v];
 }
 

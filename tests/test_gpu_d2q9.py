@@ -75,8 +75,8 @@ def test_every_variant_is_identical(prec, shape):
         sim.variant = v
         try:
             sim.step(7)
-        except rlb.RLBError as e:  # strip rounds need members narrow enough for a block
-            assert e.code == -7 and "strips" in names[v]
+        except rlb.RLBError as e:  # rounds whose windows leave no owned cell
+            assert e.code == -7 and ("strips" in names[v] or "tiles" in names[v])
             sim.close()
             continue
         f, g = [t.cpu().numpy() for t in sim.populations()]
@@ -250,8 +250,8 @@ def test_corrected_variants_identical(shape):
         sim.variant = v
         try:
             sim.step(6)
-        except rlb.RLBError as e:  # strip rounds need members narrow enough for a block
-            assert e.code == -7 and "strips" in sim.kernel_name
+        except rlb.RLBError as e:  # rounds whose windows leave no owned cell
+            assert e.code == -7 and ("strips" in sim.kernel_name or "tiles" in sim.kernel_name)
             sim.close()
             continue
         g = sim.populations()[1].cpu().numpy()
@@ -350,3 +350,90 @@ def test_sec5_cases_on_strip_rounds_400_steps(prec, tol):
         err = compare(gs, st, st.fields())
         say("  ", c.name, err)
         assert err["f"] < tol and err["g"] < tol and err["u"] < tol and err["eps"] < tol, err
+
+
+# ---------------------------------------------------------------------------
+# Tile rounds on the lattice path: windows with halos in LDS, H steps a
+# launch (k_d2q9_tiles)
+# ---------------------------------------------------------------------------
+TILE_SHAPES = [(160, 130, (0, 1, 0)), (45, 700, (1, 0, 0)), (1000, 20, (0, 1, 0)),
+               (130, 127, (0, 0, 0)), (4096, 4, (0, 0, 0))]
+
+
+@pytest.mark.parametrize("corr", [0, 1], ids=["plain", "c7"])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("shape", TILE_SHAPES, ids=lambda s: f"{s[0]}x{s[1]}_bc{s[2]}")
+def test_tile_rounds_identical_to_one_step_kernel(shape, prec, corr):
+    """Every tile-round variant (H = 2 or 3 steps a launch, partial last
+    rounds, periodic and zero-gradient faces, an axis shorter than the
+    window, 2H halo rows with the correction term) gives the populations and
+    the diagnostics sums of the one-step lattice kernel, which the tests
+    above check against the oracle; variants whose windows leave no owned
+    cell are refused."""
+    import paper_1211_3286_amd as rlb
+    nx, ny, bc = shape
+    prob = _problem(nx, ny, bc, seed=21)
+    prob.params.correction = corr
+    T = 7
+    sim = rlb.from_problems(prob, precision=prec, diag_every=3)
+    names = sim.variants()
+    assert "lattice" in names[0]
+    sim.variant = 0
+    sim.step(T)
+    ref = [t.cpu().numpy() for t in sim.populations()]
+    dref, _, _ = sim.diagnostics()
+    sim.close()
+    ran = 0
+    for v, name in enumerate(names):
+        if "tiles" not in name:
+            continue
+        s2 = rlb.from_problems(prob, precision=prec, diag_every=3)
+        s2.variant = v
+        try:
+            s2.step(T)
+        except rlb.RLBError as e:
+            # refused: a 64 x 8 window leaves no owned row with the 2H halo of
+            # the correction term; FP64 with the correction term does not fit
+            # a 1024-cell window in LDS
+            big = ",32,32>" in name or ",64,16>" in name
+            assert e.code == -7 and corr and (",64,8>" in name or (prec == FP64 and big)), name
+            s2.close()
+            continue
+        f, g = [t.cpu().numpy() for t in s2.populations()]
+        d, step, nbad = s2.diagnostics()
+        say("tile variant", name, shape, "prec", prec, "corr", corr)
+        assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
+        assert step == T and nbad == 0
+        assert relmax(d, dref) < 1e-13, (name, d, dref)
+        ran += 1
+        s2.close()
+    assert ran >= (1 if corr and prec == FP64 else 5)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_tile_rounds_with_per_cell_taus(prec):
+    """Tile rounds with relaxation times from eta/s, against the one-step
+    kernel bit for bit and the oracle."""
+    import paper_1211_3286_amd as rlb
+    prob = _problem(150, 140, (0, 1, 0), seed=22)
+    prob.params.eta_s, prob.params.kappa = 0.05, 4 / 3
+    prob.params.a_e, prob.params.a_eps = 0.3, 0.6
+    T = 11
+    sim = rlb.from_problems(prob, precision=prec)
+    names = sim.variants()
+    sim.variant = 0
+    sim.step(T)
+    ref = [t.cpu().numpy() for t in sim.populations()]
+    (gs,), _, bad = gpu_state(sim, prob)
+    st = oracle.run(prob, T)
+    err = compare(gs, st, st.fields())
+    assert bad == 0 and err["f"] < TOL[prec] and err["g"] < TOL[prec], err
+    sim.close()
+    for v, name in enumerate(names):
+        if "tiles" in name:
+            s2 = rlb.from_problems(prob, precision=prec)
+            s2.variant = v
+            s2.step(T)
+            f, g = [t.cpu().numpy() for t in s2.populations()]
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
+            s2.close()
