@@ -69,6 +69,17 @@ def test_workspace_size_of_the_largest_cube():
     assert c == 0 and b > 40.8e9
 
 
+@pytest.mark.parametrize("prec,nz_ok", [(rlb.FP32, 1023), (rlb.FP64, 511)])
+def test_workspace_size_at_the_32_bit_plane_limit(prec, nz_ok):
+    """Population byte offsets within a plane are 32-bit in the kernels: the
+    largest lattices whose plane (cells rounded up to 64, plus 64) stays
+    below 4 GiB are accepted, one more z-plane is refused (RLB_E_UNSUPPORTED)."""
+    c, b = _size([_p(nx=1024, ny=1024, nz=nz_ok)], rlb.options(prec))
+    assert c == 0 and b > 2 * 38 * 1024 * 1024 * nz_ok * (4 if prec == rlb.FP32 else 8)
+    c, _ = _size([_p(nx=1024, ny=1024, nz=nz_ok + 1)], rlb.options(prec))
+    assert c == -7
+
+
 @pytest.mark.parametrize("kw,code", [
     (dict(nx=0), -1), (dict(nz=-3), -1), (dict(bc=(0, 2, 0)), -1),
     (dict(tau_v=0.5), -2), (dict(tau_e=0.3), -2), (dict(tau_eps=float("nan")), -2),
