@@ -20,8 +20,9 @@ using rlb::MemberDesc;
 namespace {
 
 constexpr size_t kAlign = 256;
-// A single lattice at least this large runs one fused launch per step; smaller
-// lattices and batches run the persistent per-member kernel.
+// A single lattice at least this large takes the lattice path (one fused
+// launch per step, or D2Q9 tile rounds); smaller lattices and batches take the
+// persistent path (per-member kernels, segments, tube or strip rounds).
 constexpr int64_t kLatticeMinCells = 16384;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -34,7 +35,7 @@ struct Layout {
   size_t off_stage = 0, off_segs = 0, off_flags = 0, off_tape = 0, total = 0;
   int max_parts = 0;
   int export_parts = 0;  // blocks of the field export (its own partials region)
-  int64_t max_segs = 0;  // persistent path: one segment per z-plane at most
+  int64_t max_segs = 0;  // persistent path: one segment per z-plane (D2Q9: per row) at most
   rlb::TapeLayout tape;
 };
 
@@ -228,7 +229,8 @@ struct rlb_sim {
   int cur = 0;
   bool d2 = false;  // D2Q9 model (9 velocities, 18 planes per buffer)
   bool corr = false;  // D2Q9 with the correction term of Eqs. (37)-(38)
-  bool ext = false;    // some member takes its relaxation times from eta/s per cell
+  bool ext = false;    // some member takes its relaxation times from eta/s per cell or
+                       // has the general equation of state (the EXT kernels)
   int q = 19;
   bool lattice = false;
   LatticeGeom geom{};
@@ -247,8 +249,9 @@ struct rlb_sim {
   unsigned long long* d_flags = nullptr;
   int* d_error = nullptr;
   unsigned long long epoch = 0;  // steps every segment flag holds
-  int seg_built = -1;             // segment (or tube) variant the device table describes
-  hipGraph_t tgraph = nullptr;    // chain of tube rounds of the last rlb_step
+  int seg_built = -1;             // variant the device segment table describes (segments:
+                                  // sv; tube rounds: 1000 + tv; strip rounds: 2000 + sv)
+  hipGraph_t tgraph = nullptr;    // chain of tube (or strip) rounds of the last rlb_step
   hipGraphExec_t tgexec = nullptr;
   bool all_tubes = false;
   int nseg = 0;
