@@ -59,3 +59,42 @@ def compare(gpu: dict, st, F: dict) -> dict:
             "n": relmax(gpu["n"], F["n"]), "eps": relmax(gpu["eps"], F["eps"]),
             "P": relmax(gpu["P"], F["P"]), "gamma": relmax(gpu["gamma"], F["gamma"]),
             "u": float(np.abs(gpu["u"] - F["u"]).max())}
+
+
+def variants_equal_variant0(problems, precision, kinds, nsteps, tol, refused=lambda name: False):
+    """Run variant 0 of ``problems`` for ``nsteps`` steps and check it against
+    the oracle within ``tol``; then every variant whose name contains one of
+    ``kinds`` must give the same populations bit for bit (or be refused with
+    RLB_E_UNSUPPORTED where ``refused(name)``). Returns the names that ran."""
+    import oracle
+    import paper_1211_3286_amd as rlb
+    sim = rlb.from_problems(problems, precision=precision)
+    names = sim.variants()
+    sim.variant = 0
+    sim.step(nsteps)
+    ref = [t.cpu().numpy() for t in sim.populations()]
+    states, _, bad = gpu_state(sim, problems)
+    assert bad == 0
+    for p, gs in zip(problems if isinstance(problems, (list, tuple)) else [problems], states):
+        st = oracle.run(p, nsteps)
+        err = compare(gs, st, st.fields())
+        assert err["f"] < tol and err["g"] < tol, (p.name, err)
+    sim.close()
+    ran = []
+    for v, name in enumerate(names):
+        if not any(k in name for k in kinds):
+            continue
+        s2 = rlb.from_problems(problems, precision=precision)
+        s2.variant = v
+        try:
+            s2.step(nsteps)
+        except rlb.RLBError as e:
+            assert e.code == -7 and refused(name), name
+            s2.close()
+            continue
+        f, g = [t.cpu().numpy() for t in s2.populations()]
+        say("  variant", name, "prec", precision)
+        assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
+        ran.append(name)
+        s2.close()
+    return ran

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_helpers import compare, gpu_run, gpu_state, say
+from gpu_helpers import compare, gpu_run, gpu_state, say, variants_equal_variant0
 
 pytestmark = pytest.mark.gpu
 
@@ -146,3 +146,14 @@ def test_extended_persistent_kernels_stay_at_512_threads():
             with pytest.raises(rlb.RLBError) as ei:
                 s2.step(1)
             assert ei.value.code == -7
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_d2q9_rounds_with_the_general_eos(prec):
+    """Strip rounds (a batch of narrow members) and tile rounds (one lattice)
+    under P = (Gamma - 1)(eps - m n): bit for bit the one-block / one-step
+    kernels, which match the oracle."""
+    members = [_random(4, 300, 1, (0, 1, 0), "d2q9"), _random(3, 170, 1, (0, 0, 0), "d2q9")]
+    assert len(variants_equal_variant0(members, prec, ("strips",), 13, TOL[prec])) == 6
+    lat = _random(150, 130, 1, (0, 1, 0), "d2q9")
+    assert len(variants_equal_variant0([lat], prec, ("tiles",), 13, TOL[prec])) == 6

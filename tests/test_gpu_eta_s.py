@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_helpers import compare, gpu_run, gpu_state, say
+from gpu_helpers import compare, gpu_run, gpu_state, say, variants_equal_variant0
 
 pytestmark = pytest.mark.gpu
 
@@ -141,3 +141,24 @@ def test_tube_rounds_with_per_cell_taus(prec, tol):
             checked += 1
             sim.close()
     assert checked >= 3
+
+
+@pytest.mark.parametrize("corr", [0, 1], ids=["plain", "c7"])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_d2q9_rounds_with_per_cell_taus(prec, corr):
+    """Strip rounds (a batch of narrow members) and tile rounds (one lattice)
+    with relaxation times from eta/s, with and without the correction term:
+    bit for bit the one-block / one-step kernels, which match the oracle."""
+    members = [_random(4, 300, 1, (0, 1, 0), "d2q9", kappa=4 / 3),
+               _random(3, 170, 1, (0, 0, 0), "d2q9", kappa=4 / 3)]
+    for m in members:
+        m.params.correction = corr
+    ran = variants_equal_variant0(members, prec, ("strips",), 13, TOL[prec])
+    assert len(ran) == 6
+    lat = _random(150, 130, 1, (0, 1, 0), "d2q9", kappa=4 / 3)
+    lat.params.correction = corr
+    big = lambda n: ",32,32>" in n or ",64,16>" in n
+    ran = variants_equal_variant0(
+        [lat], prec, ("tiles",), 13, TOL[prec],
+        refused=lambda n: corr and (",64,8>" in n or (prec == FP64 and big(n))))
+    assert len(ran) >= (1 if corr and prec == FP64 else 5)
