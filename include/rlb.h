@@ -176,11 +176,13 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
                     size_t workspace_bytes, void* hip_stream);
 
 /* Advance every member by nsteps >= 0 steps, asynchronously on the stream.
- * Single-member lattices run one fused kernel launch per step; batches (and
- * small single lattices) run in a HIP graph, either all nsteps inside one
- * persistent launch, or as rounds of H steps on segments held in LDS (1 x 1 x L
- * tubes; narrow D2Q9 members cut into rows), by the selected variant. The
- * variants give identical results. No validation per step: cells that
+ * Single-member lattices run one fused kernel launch per step (D2Q9: or
+ * rounds of H steps on tiles held in LDS); batches (and small single
+ * lattices) run in a HIP graph, either all nsteps inside one persistent
+ * launch, or as rounds of H steps on segments held in LDS (1 x 1 x L tubes;
+ * narrow D2Q9 members cut into rows), by the selected variant (rlb_tune picks
+ * the fastest). The variants give identical results, bit for bit. No
+ * validation per step: cells that
  * become inadmissible (E <= 0 or |M| >= E) keep their populations uncollided
  * and are counted; the count is reported by rlb_moments/rlb_diagnostics. */
 rlb_status rlb_step(rlb_handle h, int32_t nsteps);
