@@ -23,15 +23,18 @@ namespace {
 // -------------------------------------------------------------------------
 // Fused step on one lattice: grid (ceil(nx/BX), ceil(ny/BY), ceil(nz/CZ)),
 // block (BX, BY); each thread updates CZ cells along z. EXT: relaxation times
-// of each cell from eta/s.
+// of each cell from eta/s. Tiles are taken in the row-per-XCD order of
+// block_tile.
 // -------------------------------------------------------------------------
 template <typename T, int BX, int BY, int CZ, bool DIAG, bool EXT>
 __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
                                                         unsigned long long* __restrict__ bad) {
-  const int x = blockIdx.x * BX + threadIdx.x;
-  const int y = blockIdx.y * BY + threadIdx.y;
+  int bx, by, bz;
+  block_tile(bx, by, bz);
+  const int x = bx * BX + threadIdx.x;
+  const int y = by * BY + threadIdx.y;
   const int tid = threadIdx.y * BX + threadIdx.x;
   const bool act = (x < geo.nx) && (y < geo.ny);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -39,7 +42,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
   const uint32_t esz = sizeof(T);
 #pragma unroll 1
   for (int k = 0; k < CZ; ++k) {
-    const int z = blockIdx.z * CZ + k;
+    const int z = bz * CZ + k;
     if (act && z < geo.nz) {
       uint32_t off[19], self;
       pull_offsets(x, y, z, geo.nx, geo.ny, geo.nz, geo.bcx, geo.bcy, geo.bcz, 0u, esz, off,

@@ -32,7 +32,8 @@ __device__ __forceinline__ void c7_neighbours(const T* __restrict__ src, int64_t
 
 // -------------------------------------------------------------------------
 // Fused step on one nx x ny lattice: grid (ceil(nx/BX), ceil(ny/(BY*CY))),
-// block (BX, BY); each thread updates CY cells along y. CORR adds the
+// block (BX, BY), tiles in the row-per-XCD order of block_tile; each thread
+// updates CY cells along y. CORR adds the
 // correction of Eqs. (37)-(38) (each cell recovers its two y-neighbours from
 // their pulled populations: 18 more loads, mostly L2 hits).
 // -------------------------------------------------------------------------
@@ -41,14 +42,16 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
                                                         unsigned long long* __restrict__ bad) {
-  const int x = blockIdx.x * BX + threadIdx.x;
+  int bx, by, bz;
+  block_tile(bx, by, bz);
+  const int x = bx * BX + threadIdx.x;
   const int tid = threadIdx.y * BX + threadIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int nbad = 0;
   const uint32_t esz = sizeof(T);
 #pragma unroll 1
   for (int k = 0; k < CY; ++k) {
-    const int y = (blockIdx.y * CY + k) * BY + threadIdx.y;
+    const int y = (by * CY + k) * BY + threadIdx.y;
     if (x < geo.nx && y < geo.ny) {
       d2q9::C7Fields fm, fp;
       if constexpr (CORR)
