@@ -32,8 +32,9 @@ __device__ __forceinline__ void c7_neighbours(const T* __restrict__ src, int64_t
 
 // -------------------------------------------------------------------------
 // Fused step on one nx x ny lattice: grid (ceil(nx/BX), ceil(ny/(BY*CY))),
-// block (BX, BY), tiles in the row-per-XCD order of block_tile; each thread
-// updates CY cells along y. CORR adds the
+// block (BX, BY); each thread updates CY cells along y. (With a multiple of 8
+// tiles per row, the plain order already keeps each tile column on one XCD,
+// so the rows a tile pulls from above and below are L2 hits.) CORR adds the
 // correction of Eqs. (37)-(38) (each cell recovers its two y-neighbours from
 // their pulled populations: 18 more loads, mostly L2 hits).
 // -------------------------------------------------------------------------
@@ -42,16 +43,14 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
                                                         unsigned long long* __restrict__ bad) {
-  int bx, by, bz;
-  block_tile(bx, by, bz);
-  const int x = bx * BX + threadIdx.x;
+  const int x = blockIdx.x * BX + threadIdx.x;
   const int tid = threadIdx.y * BX + threadIdx.x;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   int nbad = 0;
   const uint32_t esz = sizeof(T);
 #pragma unroll 1
   for (int k = 0; k < CY; ++k) {
-    const int y = (by * CY + k) * BY + threadIdx.y;
+    const int y = (blockIdx.y * CY + k) * BY + threadIdx.y;
     if (x < geo.nx && y < geo.ny) {
       d2q9::C7Fields fm, fp;
       if constexpr (CORR)
@@ -325,8 +324,10 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
   __shared__ T lds[18][NT];
   __shared__ double cf[CORR ? 4 : 1][CORR ? NT : 1];  // x1, gamma, sigma u^2, sigma u
   __shared__ int cok[CORR ? NT : 1];
-  const AxisWindow X = axis_window(blockIdx.x, a.nx, TX, a.ox, a.hx, a.bcx);
-  const AxisWindow Y = axis_window(blockIdx.y, a.ny, TY, a.oy, a.hy, a.bcy);
+  int bx, by, bz;
+  block_tile(bx, by, bz);  // the tiles of a row on one XCD: their windows overlap in x
+  const AxisWindow X = axis_window(bx, a.nx, TX, a.ox, a.hx, a.bcx);
+  const AxisWindow Y = axis_window(by, a.ny, TY, a.oy, a.hy, a.bcy);
   const int tid = threadIdx.x;
   bool live[CPT], owned[CPT];
   int64_t gi[CPT];
