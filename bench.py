@@ -588,6 +588,8 @@ def main():
         forms["fp64" if other == rlb.FP64 else "fp32"] = {
             k: o[k] for k in ("mlups", "ms_per_step", "achieved_gbs", "frac", "kernel",
                               "conservation_drift")}
+        forms["fp64" if other == rlb.FP64 else "fp32"]["traffic"] = measured_traffic(
+            o["kernel"], o["cells"])
         log("other precision", forms)
         forms["batched"] = bench_batched(torch, rlb, wl)
         log("batched", forms["batched"])
