@@ -10,6 +10,15 @@
   particle number obeys a diffusion equation with phi = c_s^2 (tau_f - dt/2).
 * Bulk relaxation trend: a sound wave is damped more when tau_e grows (the
   bulk viscosity after Eq. 36 grows with tau_e - dt/2).
+* Sound attenuation, quantitatively: at rest with P = eps/3 (chi = 0), a
+  small plane sound wave along y obeys the linearised Eqs. (24)-(25) with
+  Pi_yy = ((2 - 2/D) eta + varsigma) d_y u, which gives omega = +-k c_s - i G,
+  G = ((2 - 2/D) eta + varsigma) k^2 / (2 (eps + P)). D2Q9 (Eq. 36, D = 2):
+  eta = (tau_v - 1/2) c_s^2 sigma, varsigma = (tau_e - 1/2) c_s^2 sigma, so
+  G = k^2 (tau_v + tau_e - 1) / 6. D3Q19 (D = 3): the same expansion of the
+  moment basis gives varsigma = (2/3)(tau_e - 1/2) c_s^2 sigma, so
+  G = k^2 ((4/3)(tau_v - 1/2) + (2/3)(tau_e - 1/2)) / 6. The frequency is
+  k c_s with c_s^2 = 1/3.
 """
 
 import numpy as np
@@ -120,6 +129,33 @@ def test_bulk_relaxation_damps_sound(orc):
         # acoustic energy: pressure and momentum fluctuations
         amps.append(np.abs(F["eps"] - F["eps"].mean()).max() + np.abs(F["u"][2]).max())
     assert amps[0] > amps[1] > amps[2]
+
+
+@pytest.mark.parametrize("lattice,tau_v,tau_e", [("d2q9", 0.8, 0.55), ("d2q9", 0.6, 1.0),
+                                                  ("d3q19", 0.8, 0.55), ("d3q19", 1.2, 0.7)])
+def test_sound_attenuation_matches_the_bulk_and_shear_viscosities(orc, lattice, tau_v, tau_e):
+    from scipy.optimize import curve_fit
+    L, T, amp = 128, 1200, 1e-4
+    k = 2 * np.pi / L
+    prob = wl.uniform(1, L, 1, n=1.0, eps=1.0, tau_f=0.8, tau_v=tau_v, tau_e=tau_e,
+                      tau_eps=0.9)
+    prob.params.lattice = lattice
+    y = np.arange(L)
+    prob.eps[0, :, 0] = 1.0 + amp * np.cos(k * y)
+    st = orc.State.init(prob)
+    a = np.empty(T)
+    for t in range(T):
+        st.step(1)
+        a[t] = 2.0 / L * ((st.fields()["eps"][0, :, 0] - 1.0) * np.cos(k * y)).sum()
+    t = np.arange(1, T + 1)
+    (A, G, w, p), _ = curve_fit(lambda t, A, G, w, p: A * np.exp(-G * t) * np.cos(w * t + p), t,
+                                a, p0=[amp, 1e-4, k / np.sqrt(3.0), 0.0], maxfev=20000)
+    if lattice == "d2q9":
+        want = k * k / 6.0 * (tau_v + tau_e - 1.0)
+    else:
+        want = k * k / 6.0 * (4.0 / 3.0 * (tau_v - 0.5) + 2.0 / 3.0 * (tau_e - 0.5))
+    assert abs(G / want - 1.0) < 2e-3, (G, want)
+    assert abs(w / (k / np.sqrt(3.0)) - 1.0) < 1e-3
 
 
 def test_particle_bump_is_carried_by_the_flow(orc):
