@@ -523,11 +523,63 @@ def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict
     return out
 
 
+def d2q9_traffic(fetch_csv: str, write_csv: str, n: int = 4096) -> dict:
+    """HBM bytes of the D2Q9 lattice-path kernels on the n x n lattice from two
+    PMC runs (FETCH_SIZE, WRITE_SIZE), scaled as in write_traffic: per launch
+    for the one-step kernels (against 2 x 18 values per cell), and per cell
+    update for the tile rounds, whose launches advance H steps (H recovered
+    from the number of tiles in the launch grid)."""
+    import collections
+    import csv
+    vals = collections.defaultdict(list)
+    for path in (fetch_csv, write_csv):
+        for r in csv.DictReader(open(path)):
+            vals[(r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"])].append(
+                float(r["Counter_Value"]) * 1024.0)
+    copy = {c: sum(v) / len(v) for (k, g, c), v in vals.items()
+            if "copyBuffer" in k and g == 131072}
+    scale = {c: (1 << 30) / copy[c] for c in copy}
+    recs = collections.defaultdict(dict)
+    for (k, g, c), v in vals.items():
+        m = re.search(r"k_d2q9_(lattice|tiles)<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+)", k)
+        if not m:
+            continue
+        kind, typ, a1, a2, a3, f1, f2 = m.groups()
+        recs[(kind, typ, int(a1), int(a2), int(a3), f1, f2, g)][c] = sum(v) / len(v) * scale[c]
+    cells = n * n
+    out = {"lattice": f"{n}x{n}", "calibration": scale, "kernels": {}}
+    for (kind, typ, a1, a2, a3, f1, f2, g), r in sorted(recs.items()):
+        if "FETCH_SIZE" not in r or "WRITE_SIZE" not in r:
+            continue
+        esz = 4 if typ == "float" else 8
+        total = r["FETCH_SIZE"] + r["WRITE_SIZE"]
+        if kind == "lattice":  # <T, BX, BY, CY, DIAG, CORR, EXT>
+            if f1 == "true":
+                continue  # the launches with fused diagnostics
+            name = f"k_d2q9_lattice<{typ},{a1},{a2},{a3}>" + ("+c7" if f2 == "true" else "")
+            out["kernels"][name] = {"bytes_per_launch": total,
+                                    "ratio": total / (2 * 18 * esz * cells)}
+        else:  # <T, TX, TY, NTH, CORR, EXT>
+            tiles = g // a3
+            corr = f1 == "true"
+            H = next((h for h in range(1, 9)
+                      if -(-n // (a1 - 2 * h)) * -(-n // (a2 - 2 * (2 * h if corr else h)))
+                      == tiles), None)
+            if H is None:
+                continue
+            name = f"k_d2q9_tiles<{typ},{a1},{a2}>/h{H}" + ("+c7" if corr else "")
+            out["kernels"][name] = {"bytes_per_launch": total,
+                                    "bytes_per_cell_update": total / (cells * H),
+                                    "one_step_bytes_per_cell_update": 2 * 18 * esz}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # the 256^3 run is 500 steps: 50 untimed, then 450 timed
+    ap.add_argument("--steps", type=int, default=450)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -535,6 +587,9 @@ def main():
                     help="time the CPU oracle on every configuration (all cores and one "
                          "core), print one JSON line and exit")
     ap.add_argument("--no-forms", action="store_true", help="only the headline FP32 step")
+    ap.add_argument("--forms", default="",
+                    help="comma list of the forms to run besides the headline (default: all): "
+                         "fp64, batched, adjoint, blast_512, d2q9, eta_s, copy_ceiling")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--diag-every", type=int, default=50,
                     help="fuse the FP64 conservation sums into every N-th step")
@@ -542,6 +597,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--d2q9-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the HBM bytes of the D2Q9 kernels from two PMC runs and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two PMC runs and exit")
     args = ap.parse_args()
@@ -550,6 +607,9 @@ def main():
         return
     if args.oracle_sweep:
         print(json.dumps(cpu_baseline_sweep()), flush=True)
+        return
+    if args.d2q9_traffic:
+        print(json.dumps(d2q9_traffic(*args.d2q9_traffic), indent=1))
         return
     if args.write_traffic:
         rec = write_traffic(*args.write_traffic)
@@ -581,26 +641,27 @@ def main():
             "kernel": head["kernel"], "algorithmic_bytes_per_launch":
                 head["bytes_per_cell"] * head["cells"]}
     forms = {}
-    if not args.no_forms:
-        other = rlb.FP64 if prec == rlb.FP32 else rlb.FP32
+    sel = set(args.forms.split(",")) if args.forms else None
+
+    def want(name):
+        return not args.no_forms and (sel is None or name in sel)
+
+    other = rlb.FP64 if prec == rlb.FP32 else rlb.FP32
+    oname = "fp64" if other == rlb.FP64 else "fp32"
+    if want(oname):
         o = bench_lattice(torch, rlb, wl, args.size, other, max(args.steps // 2, 10),
                           max(args.warmup // 2, 2), args.diag_every)
-        forms["fp64" if other == rlb.FP64 else "fp32"] = {
-            k: o[k] for k in ("mlups", "ms_per_step", "achieved_gbs", "frac", "kernel",
-                              "conservation_drift")}
-        forms["fp64" if other == rlb.FP64 else "fp32"]["traffic"] = measured_traffic(
-            o["kernel"], o["cells"])
+        forms[oname] = {k: o[k] for k in ("mlups", "ms_per_step", "achieved_gbs", "frac",
+                                          "kernel", "conservation_drift")}
+        forms[oname]["traffic"] = measured_traffic(o["kernel"], o["cells"])
         log("other precision", forms)
-        forms["batched"] = bench_batched(torch, rlb, wl)
-        log("batched", forms["batched"])
-        forms["adjoint"] = bench_adjoint(torch, rlb, wl)
-        log("adjoint", forms["adjoint"])
-        forms["blast_512"] = bench_blast(torch, rlb, wl)
-        log("blast", forms["blast_512"])
-        forms["d2q9"] = bench_d2q9(torch, rlb, wl)
-        log("d2q9", forms["d2q9"])
-        forms["eta_s"] = bench_eta_s(torch, rlb, wl)
-        log("eta_s", forms["eta_s"])
+    runs = (("batched", bench_batched), ("adjoint", bench_adjoint), ("blast_512", bench_blast),
+            ("d2q9", bench_d2q9), ("eta_s", bench_eta_s))
+    for name, fn in runs:
+        if want(name):
+            forms[name] = fn(torch, rlb, wl)
+            log(name, forms[name])
+    if want("copy_ceiling"):
         # the runtime's own device-to-device copy of the bytes one FP32 step
         # moves (38 x 4 B per cell read, the same written): a practical
         # bandwidth ceiling to read the roofline fraction against

@@ -44,6 +44,24 @@ __device__ __forceinline__ void block_tile(int& bx, int& by, int& bz) {
   bz = row / gy;
 }
 
+// Band order of a 2D grid (gx, gy) with gx a multiple of 8 (else the plain
+// order): XCD j runs the band of tile columns [j gx/8, (j+1) gx/8), row by
+// row, so that both the x-neighbours (adjacent ids) and the y-neighbours
+// (gx/8 ids apart) of a tile share its L2, while the 8 XCDs work in the same
+// rows a band apart. One to one.
+__device__ __forceinline__ void block_tile_bands(int& bx, int& by) {
+  const int gx = gridDim.x;
+  bx = blockIdx.x;
+  by = blockIdx.y;
+  if (gx >= 8 && (gx & 7) == 0) {
+    const int h = blockIdx.x + gx * blockIdx.y;
+    const int w = gx >> 3;  // tile columns per band
+    const int k = h >> 3;   // position in the XCD's sequence
+    bx = (h & 7) * w + k % w;
+    by = k / w;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T ld(const T* plane, uint32_t byteoff) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(plane) + byteoff);
