@@ -773,8 +773,14 @@ rlb_status persistent_error(rlb_sim* h) {
 // ============================================================================
 extern "C" {
 
+static_assert(sizeof(rlb_status) == sizeof(int32_t), "rlb_status travels as a 32-bit int");
+
 const char* rlb_status_string(rlb_status s) {
-  switch (s) {
+  // A C caller may pass any int: read it as one (loading an enum object that
+  // holds a value outside the enumeration's range is undefined in C++).
+  int32_t code;
+  std::memcpy(&code, &s, sizeof(code));
+  switch (code) {
     case RLB_OK: return "ok";
     case RLB_E_ARG: return "invalid argument";
     case RLB_E_TAU: return "relaxation time must be finite and > 1/2";
