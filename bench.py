@@ -507,10 +507,12 @@ def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict
     scale = {c: (1 << 30) / copy[c] for c in copy}
     out = {"_calibration": {"copy_bytes": 1 << 30, "counter_bytes": copy, "scale": scale}}
     for (k, g, c), v in vals.items():
-        if "k_step_lattice" not in k or ", true>" in k:  # the eta/s kernels are not priced
+        # k_step_lattice<T, BX, BY, CZ, DIAG, EXT, NTS>: the launches with fused
+        # diagnostics and the eta/s kernels are not priced
+        m = re.search(r"k_step_lattice<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+), (\w+)>", k)
+        if not m or m.group(5) == "true" or m.group(6) == "true":
             continue
-        name = k.replace("void rlb::(anonymous namespace)::", "").split("(")[0]
-        name = re.sub(r"(,(true|false))+>", ">", name.replace(", ", ","))
+        name = "k_step_lattice<{},{},{},{}>".format(*m.groups()[:4])
         rec = out.setdefault(name, {"cells": cells, "source_hash": kernel_hash()})
         rec[c.lower() + "_bytes"] = sum(v) / len(v) * scale[c]
     for name, rec in out.items():

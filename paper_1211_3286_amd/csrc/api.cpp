@@ -24,6 +24,8 @@ constexpr size_t kAlign = 256;
 // launch per step, or D2Q9 tile rounds); smaller lattices and batches take the
 // persistent path (per-member kernels, segments, tube or strip rounds).
 constexpr int64_t kLatticeMinCells = 16384;
+// Double-buffered states up to this size are stored with plain stores.
+constexpr size_t kCachedStateBytes = size_t(1) << 30;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -945,6 +947,11 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     h->geom.rt = d.rt;
     h->geom.ref = d.ref;
     h->geom.ext = d.ext;
+    // Plain stores in the one-step kernels while the double-buffered state is
+    // at most 1 GiB (measured on D3Q19 FP32 planar lattices: 25-37 % faster
+    // at 80-160 MB, even at 320 MB, 10 % faster at 640 MB; nontemporal stores
+    // 4-5 % faster from 1.3 GB up, e.g. the 5.1 GB of 256^3).
+    h->geom.cached_store = 2 * (L.off_buf1 - L.off_buf0) <= kCachedStateBytes ? 1 : 0;
   }
   h->cur = 0;
   if (opt->ckpt_every > 0) {

@@ -29,6 +29,10 @@ struct LatticeGeom {
   Rates rt;
   Ref ref;
   Ext ext;  // eta/s relaxation times and equation of state (EXT kernels, init, export)
+  // 1: the one-step lattice kernels store with plain (cached) stores, so that
+  // a state small enough for the memory-side cache is read back from it next
+  // step; 0: nontemporal stores
+  int32_t cached_store;
 };
 
 struct LatticeVariant {

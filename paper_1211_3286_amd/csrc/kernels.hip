@@ -24,9 +24,13 @@ namespace {
 // Fused step on one lattice: grid (ceil(nx/BX), ceil(ny/BY), ceil(nz/CZ)),
 // block (BX, BY); each thread updates CZ cells along z. EXT: relaxation times
 // of each cell from eta/s. Tiles are taken in the row-per-XCD order of
-// block_tile.
+// block_tile. NTS: nontemporal stores; without, plain stores, which the host
+// picks when the double-buffered state fits the memory-side cache, so that the
+// next step reads it back from there. (The store kind is a template argument:
+// two store loops that differ only in the hint behind a run-time branch get
+// merged by the compiler, which keeps the plain form.)
 // -------------------------------------------------------------------------
-template <typename T, int BX, int BY, int CZ, bool DIAG, bool EXT>
+template <typename T, int BX, int BY, int CZ, bool DIAG, bool EXT, bool NTS>
 __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ src,
                                                         T* __restrict__ dst, LatticeGeom geo,
                                                         double* __restrict__ partials,
@@ -61,8 +65,13 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
         for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
 #pragma unroll
       for (int a = 0; a < 19; ++a) {
-        st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
-        st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+        if constexpr (NTS) {
+          st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+          st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+        } else {
+          st(dst + (int64_t)a * geo.cs, self, f[a]);
+          st(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+        }
       }
     }
   }
@@ -523,17 +532,27 @@ int grid_for(int64_t n) {
   return (int)b;
 }
 
+template <typename T, int BX, int BY, int CZ, bool EXT, bool NTS>
+void lat_launch_stores(bool diag, dim3 grid, dim3 block, const void* src, void* dst,
+                       const LatticeGeom& g, double* partials, unsigned long long* bad,
+                       hipStream_t s) {
+  if (diag)
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, EXT, NTS>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
+  else
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, EXT, NTS>), grid, block, 0, s,
+                       (const T*)src, (T*)dst, g, partials, bad);
+}
+
 template <typename T, int BX, int BY, int CZ, bool EXT>
 hipError_t lat_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
                       double* partials, unsigned long long* bad, hipStream_t s) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + CZ - 1) / CZ);
-  if (diag)
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, EXT>), grid, block, 0, s,
-                       (const T*)src, (T*)dst, g, partials, bad);
+  if (g.cached_store)
+    lat_launch_stores<T, BX, BY, CZ, EXT, false>(diag, grid, block, src, dst, g, partials, bad, s);
   else
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, EXT>), grid, block, 0, s,
-                       (const T*)src, (T*)dst, g, partials, bad);
+    lat_launch_stores<T, BX, BY, CZ, EXT, true>(diag, grid, block, src, dst, g, partials, bad, s);
   return hipGetLastError();
 }
 
