@@ -525,6 +525,59 @@ def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict
     return out
 
 
+# MI355X: 256 CUs of 4 SIMDs; a SIMD takes 4 cycles per wave64 VALU
+# instruction, so a CU issues at most one wave-level VALU instruction a cycle.
+CU_NUM = 256
+XCC_NUM = 8
+
+
+def valu_summary(csv_path: str, command: str) -> str:
+    """Markdown table of the VALU load of the step kernels from one rocprofv3
+    --pmc run of SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_INSTS_LDS, SQ_WAVES
+    and GRBM_GUI_ACTIVE: per kernel and launch grid, the mean over its
+    dispatches of the duration (the dispatch timestamps), the shader clock
+    (GRBM_GUI_ACTIVE, summed over the 8 XCDs, per XCD and second), the
+    issue fraction (wave-level VALU instructions over one per CU and cycle)
+    and the VALU busy fraction (SQ_ACTIVE_INST_VALU quad-cycles summed over
+    the SIMDs, over CUs x cycles, as rocprofv3's VALUBusy)."""
+    import collections
+    import csv
+
+    def short(name):
+        name = name.replace("rlb::(anonymous namespace)::", "").replace("void ", "")
+        return name.split("(")[0]
+
+    groups = collections.defaultdict(lambda: collections.defaultdict(list))
+    dur = collections.defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        name = short(r["Kernel_Name"])
+        if not name.startswith(("k_step", "k_d2q9")):
+            continue
+        key = (name, int(r["Grid_Size"]), int(r["Workgroup_Size"]))
+        groups[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[key][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    out = [f"Command: `{command}`", "",
+           "| kernel | grid (threads) | block | dispatches | average (us) | clock (GHz) | "
+           "VALU wave-instructions per dispatch | issue fraction | VALU busy | LDS / VALU |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    need = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS", "GRBM_GUI_ACTIVE")
+    rows = []
+    for key, c in groups.items():
+        if any(n not in c for n in need):
+            continue
+        mean = {n: sum(v) / len(v) for n, v in c.items()}
+        t = sum(dur[key].values()) / len(dur[key])
+        cycles = mean["GRBM_GUI_ACTIVE"] / XCC_NUM
+        rows.append((key, len(dur[key]), t, cycles / t / 1e9, mean["SQ_INSTS_VALU"],
+                     mean["SQ_INSTS_VALU"] / (CU_NUM * cycles),
+                     mean["SQ_ACTIVE_INST_VALU"] / (CU_NUM * cycles),
+                     mean["SQ_INSTS_LDS"] / max(mean["SQ_INSTS_VALU"], 1.0)))
+    for (name, grid, block), n, t, ghz, valu, issue, busy, lds in sorted(rows, key=lambda r: -r[1] * r[2]):
+        out.append(f"| `{name}` | {grid} | {block} | {n} | {t * 1e6:.1f} | {ghz:.2f} | "
+                   f"{valu:.4g} | {issue:.3f} | {busy:.3f} | {lds:.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def d2q9_traffic(fetch_csv: str, write_csv: str, n: int = 4096) -> dict:
     """HBM bytes of the D2Q9 lattice-path kernels on the n x n lattice from two
     PMC runs (FETCH_SIZE, WRITE_SIZE), scaled as in write_traffic: per launch
@@ -544,9 +597,15 @@ def d2q9_traffic(fetch_csv: str, write_csv: str, n: int = 4096) -> dict:
     recs = collections.defaultdict(dict)
     for (k, g, c), v in vals.items():
         m = re.search(r"k_d2q9_(lattice|tiles)<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+)", k)
-        if not m:
-            continue
-        kind, typ, a1, a2, a3, f1, f2 = m.groups()
+        if m:
+            kind, typ, a1, a2, a3, f1, f2 = m.groups()
+        else:
+            # k_d2q9_lattice_c7<T, BX, BY, DIAG, EXT, NTS>: one cell a thread, CORR
+            m = re.search(r"k_d2q9_lattice_c7<(\w+), (\d+), (\d+), (\w+), (\w+)", k)
+            if not m:
+                continue
+            typ, a1, a2, f1, _ = m.groups()
+            kind, a3, f2 = "lattice", "1", "true"
         recs[(kind, typ, int(a1), int(a2), int(a3), f1, f2, g)][c] = sum(v) / len(v) * scale[c]
     cells = n * n
     out = {"lattice": f"{n}x{n}", "calibration": scale, "kernels": {}}
@@ -599,6 +658,8 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("CSV", "COMMAND"),
+                    help="print the VALU load of the step kernels from one PMC run and exit")
     ap.add_argument("--d2q9-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the HBM bytes of the D2Q9 kernels from two PMC runs and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -612,6 +673,9 @@ def main():
         return
     if args.d2q9_traffic:
         print(json.dumps(d2q9_traffic(*args.d2q9_traffic), indent=1))
+        return
+    if args.valu_summary:
+        print(valu_summary(*args.valu_summary), end="")
         return
     if args.write_traffic:
         rec = write_traffic(*args.write_traffic)

@@ -276,32 +276,56 @@ __device__ __forceinline__ double c7_row(const Macro& m, const C7Fields& fm,
 // With CORR, fm / fp are the fields of the y - 1 and y + 1 neighbours and
 // the correction of Eqs. (37)-(38) is applied. EXT: relaxation times of this
 // cell from eta/s (local_rates).
+// The collision in two stages: recovered() takes the sums of the pulled
+// populations and the recovery, collide_recovered() the rest, so that a kernel
+// can publish the cell's C_7 fields (c7_fields of the recovery) in between.
+struct Recovered {
+  double N, E, Mx, My, fs, gs;
+  Macro mac;
+  bool ok;
+};
+
+template <typename C, bool EXT = false>
+__device__ __forceinline__ Recovered recovered(const C (&f)[9], const C (&g)[9], const Ref& ref,
+                                               const Ext* ext = nullptr) {
+  Recovered r;
+  d2q9::cell_sums(f, g, ref, r.N, r.E, r.Mx, r.My, r.fs, r.gs);
+  if constexpr (EXT)
+    r.ok = recover_model(r.N, r.E, r.Mx, r.My, 0.0, *ext, r.mac);
+  else
+    r.ok = recover(r.E, r.Mx, r.My, 0.0, r.mac);
+  return r;
+}
+
+template <typename C, bool CORR = false, bool EXT = false>
+__device__ __forceinline__ bool collide_recovered(C (&f)[9], C (&g)[9], const Recovered& r,
+                                                  const Rates& rt_member, const Ref& ref,
+                                                  Sums& sums, const C7Fields* fm = nullptr,
+                                                  const C7Fields* fp = nullptr,
+                                                  const Ext* ext = nullptr) {
+  sums.v[0] = r.N;
+  sums.v[1] = r.E;
+  sums.v[2] = r.Mx;
+  sums.v[3] = r.My;
+  sums.v[4] = 0.0;
+  if (!r.ok) return false;
+  Rates rt = rt_member;
+  if constexpr (EXT) rt = local_rates(rt_member, *ext, r.N, r.mac);
+  double c7 = 0.0;
+  if constexpr (CORR) c7 = d2q9::c7_row(r.mac, *fm, *fp);
+  d2q9::collide_f(f, r.N, r.fs, r.mac, rt, ref);
+  d2q9::collide_g(g, r.Mx, r.My, r.gs, r.mac, rt, ref, c7);
+  return true;
+}
+
 template <typename C, bool CORR = false, bool EXT = false>
 __device__ __forceinline__ bool collide(C (&f)[9], C (&g)[9], const Rates& rt_member,
                                         const Ref& ref, Sums& sums,
                                         const C7Fields* fm = nullptr,
                                         const C7Fields* fp = nullptr,
                                         const Ext* ext = nullptr) {
-  double N, E, Mx, My, fs, gs;
-  d2q9::cell_sums(f, g, ref, N, E, Mx, My, fs, gs);
-  sums.v[0] = N;
-  sums.v[1] = E;
-  sums.v[2] = Mx;
-  sums.v[3] = My;
-  sums.v[4] = 0.0;
-  Macro mac;
-  Rates rt = rt_member;
-  if constexpr (EXT) {
-    if (!recover_model(N, E, Mx, My, 0.0, *ext, mac)) return false;
-    rt = local_rates(rt_member, *ext, N, mac);
-  } else {
-    if (!recover(E, Mx, My, 0.0, mac)) return false;
-  }
-  double c7 = 0.0;
-  if constexpr (CORR) c7 = d2q9::c7_row(mac, *fm, *fp);
-  d2q9::collide_f(f, N, fs, mac, rt, ref);
-  d2q9::collide_g(g, Mx, My, gs, mac, rt, ref, c7);
-  return true;
+  const Recovered r = recovered<C, EXT>(f, g, ref, ext);
+  return collide_recovered<C, CORR, EXT>(f, g, r, rt_member, ref, sums, fm, fp, ext);
 }
 
 // Equilibrium deviations of a cell from its fields (Eqs. 7, 32, 33), FP64;

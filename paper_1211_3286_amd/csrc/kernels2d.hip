@@ -101,6 +101,105 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
 }
 
 // -------------------------------------------------------------------------
+// The same step with the correction term, the C_7 fields shared through LDS:
+// grid (ceil(nx/BX), ceil(ny/BY)), block (BX, BY), one cell per thread. Each
+// thread recovers the fields of its own cell from its pulled g and publishes
+// them, keeping the recovery for its own collision; the block's first and
+// last valid rows also recover the rows beyond (their y-neighbours by the
+// y-streaming rule). A cell so costs 1 + 2/BY recoveries instead of the 3 of
+// k_d2q9_lattice with the correction, whose step is VALU-bound. Results are
+// those of k_d2q9_lattice bit for bit (the same fields from the same pulled g).
+// -------------------------------------------------------------------------
+template <typename T, int BX, int BY, bool DIAG, bool EXT, bool NTS>
+__global__ __launch_bounds__(BX* BY) void k_d2q9_lattice_c7(const T* __restrict__ src,
+                                                           T* __restrict__ dst, LatticeGeom geo,
+                                                           double* __restrict__ partials,
+                                                           unsigned long long* __restrict__ bad) {
+  constexpr int R = BY + 2;  // LDS rows: the row above, BY rows, the row below
+  __shared__ double cf[4][R * BX];
+  __shared__ int cok[R * BX];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * BX + tx;
+  const int x = blockIdx.x * BX + tx;
+  const int y0 = blockIdx.y * BY;
+  const int rows = min(BY, geo.ny - y0);  // valid rows of the block (the grid makes it >= 1)
+  const int y = y0 + ty;
+  const bool xin = x < geo.nx;
+  const bool in = xin && ty < rows;
+  const uint32_t esz = sizeof(T);
+  auto publish = [&](int slot, const d2q9::C7Fields& F) {
+    cf[0][slot] = F.x1;
+    cf[1][slot] = F.gam;
+    cf[2][slot] = F.su2;
+    cf[3][slot] = F.su;
+    cok[slot] = F.ok ? 1 : 0;
+  };
+  T f[9], g[9];
+  uint32_t self = 0;
+  d2q9::Recovered rec;
+  if (in) {
+    uint32_t off[9];
+    d2q9::pull_offsets(x, y, geo.nx, geo.ny, geo.bcx, geo.bcy, 0u, esz, off, self);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
+      g[a] = ld(src + (int64_t)(9 + a) * geo.cs, off[a]);
+    }
+    // the cell's own recovery serves both its published fields and its
+    // collision (the correction needs the paper's equation of state, for which
+    // the recovery is that of c7_fields_of)
+    rec = d2q9::recovered<T, EXT>(f, g, geo.ref, &geo.ext);
+    publish((ty + 1) * BX + tx, d2q9::c7_fields(rec.mac, rec.ok));
+  }
+  if (xin && ty == 0) {  // the y-neighbour below the first row: LDS row 0
+    uint32_t off[9], s0;
+    d2q9::pull_offsets(x, nbr(y0, -1, geo.ny, geo.bcy), geo.nx, geo.ny, geo.bcx, geo.bcy, 0u,
+                       esz, off, s0);
+    publish(tx, d2q9::c7_fields_at(src, geo.cs, off, geo.ref));
+  }
+  if (xin && ty == rows - 1) {  // the y-neighbour above the last row: LDS row rows + 1
+    uint32_t off[9], s1;
+    d2q9::pull_offsets(x, nbr(y0 + rows - 1, 1, geo.ny, geo.bcy), geo.nx, geo.ny, geo.bcx,
+                       geo.bcy, 0u, esz, off, s1);
+    publish((rows + 1) * BX + tx, d2q9::c7_fields_at(src, geo.cs, off, geo.ref));
+  }
+  __syncthreads();
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int nbad = 0;
+  if (in) {
+    const int m = ty * BX + tx, p = (ty + 2) * BX + tx;
+    const d2q9::C7Fields fm{cf[0][m], cf[1][m], cf[2][m], cf[3][m], cok[m] != 0};
+    const d2q9::C7Fields fp{cf[0][p], cf[1][p], cf[2][p], cf[3][p], cok[p] != 0};
+    Sums s;
+    const bool ok = d2q9::collide_recovered<T, true, EXT>(f, g, rec, geo.rt, geo.ref, s, &fm,
+                                                          &fp, &geo.ext);
+    nbad += ok ? 0 : 1;
+    if (DIAG)
+#pragma unroll
+      for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+      if constexpr (NTS) {
+        st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+        st_nt(dst + (int64_t)(9 + a) * geo.cs, self, g[a]);
+      } else {
+        st(dst + (int64_t)a * geo.cs, self, f[a]);
+        st(dst + (int64_t)(9 + a) * geo.cs, self, g[a]);
+      }
+    }
+  }
+  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (DIAG) {
+    block_sum5<BX * BY>(acc, tid);
+    if (tid == 0) {
+      const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+#pragma unroll
+      for (int i = 0; i < 5; ++i) partials[b * 5 + i] = acc[i];
+    }
+  }
+}
+
+// -------------------------------------------------------------------------
 // Persistent step over a batch of D2Q9 members: one block per member, all
 // nsteps in the launch with a block barrier between steps.
 // -------------------------------------------------------------------------
@@ -563,7 +662,8 @@ __global__ __launch_bounds__(256) void k_d2q9_planes(const T* state, int64_t cs,
 
 // ------------------------------ variants ---------------------------------
 constexpr LatticeVariant kLat2[] = {{64, 1, 1},  {128, 1, 1}, {256, 1, 1}, {64, 4, 1},
-                                    {128, 2, 1}, {256, 1, 2}, {256, 1, 4}, {128, 2, 4}};
+                                    {128, 2, 1}, {256, 1, 2}, {256, 1, 4}, {128, 2, 4},
+                                    {64, 8, 1},  {128, 4, 1}};
 constexpr int kNumLat2 = sizeof(kLat2) / sizeof(kLat2[0]);
 constexpr MemberVariant kMem2[] = {{256, 1}, {512, 1}, {1024, 1}, {512, 2}, {1024, 2}};
 constexpr int kNumMem2 = sizeof(kMem2) / sizeof(kMem2[0]);
@@ -578,16 +678,30 @@ int grid2_for(int64_t n) {
   return (int)b;
 }
 
+// With the correction term, blocks of one cell per thread and at least 4 rows
+// share the neighbours' C_7 fields through LDS (k_d2q9_lattice_c7).
+template <int BY, int CY, bool CORR>
+constexpr bool kC7Lds = CORR && CY == 1 && BY >= 4;
+
 template <typename T, int BX, int BY, int CY, bool CORR, bool EXT, bool NTS>
 void lat2_launch_stores(bool diag, dim3 grid, dim3 block, const void* src, void* dst,
                         const LatticeGeom& g, double* partials, unsigned long long* bad,
                         hipStream_t s) {
-  if (diag)
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR, EXT, NTS>), grid, block, 0, s,
-                       (const T*)src, (T*)dst, g, partials, bad);
-  else
-    hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR, EXT, NTS>), grid, block, 0,
-                       s, (const T*)src, (T*)dst, g, partials, bad);
+  if constexpr (kC7Lds<BY, CY, CORR>) {
+    if (diag)
+      hipLaunchKernelGGL((k_d2q9_lattice_c7<T, BX, BY, true, EXT, NTS>), grid, block, 0, s,
+                         (const T*)src, (T*)dst, g, partials, bad);
+    else
+      hipLaunchKernelGGL((k_d2q9_lattice_c7<T, BX, BY, false, EXT, NTS>), grid, block, 0, s,
+                         (const T*)src, (T*)dst, g, partials, bad);
+  } else {
+    if (diag)
+      hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, true, CORR, EXT, NTS>), grid, block, 0,
+                         s, (const T*)src, (T*)dst, g, partials, bad);
+    else
+      hipLaunchKernelGGL((k_d2q9_lattice<T, BX, BY, CY, false, CORR, EXT, NTS>), grid, block, 0,
+                         s, (const T*)src, (T*)dst, g, partials, bad);
+  }
 }
 
 template <typename T, int BX, int BY, int CY, bool CORR, bool EXT>
@@ -616,6 +730,8 @@ hipError_t lat2_dispatch(int v, bool diag, const void* src, void* dst, const Lat
     case 5: return lat2_launch<T, 256, 1, 2, CORR, EXT>(diag, src, dst, g, partials, bad, s);
     case 6: return lat2_launch<T, 256, 1, 4, CORR, EXT>(diag, src, dst, g, partials, bad, s);
     case 7: return lat2_launch<T, 128, 2, 4, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 8: return lat2_launch<T, 64, 8, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
+    case 9: return lat2_launch<T, 128, 4, 1, CORR, EXT>(diag, src, dst, g, partials, bad, s);
   }
   return hipErrorInvalidValue;
 }
@@ -696,12 +812,16 @@ const char* d2q9_lattice_kernel_name(int precision, int v) {
   static const char* n32[] = {"k_d2q9_lattice<float,64,1,1>",  "k_d2q9_lattice<float,128,1,1>",
                               "k_d2q9_lattice<float,256,1,1>", "k_d2q9_lattice<float,64,4,1>",
                               "k_d2q9_lattice<float,128,2,1>", "k_d2q9_lattice<float,256,1,2>",
-                              "k_d2q9_lattice<float,256,1,4>", "k_d2q9_lattice<float,128,2,4>"};
+                              "k_d2q9_lattice<float,256,1,4>", "k_d2q9_lattice<float,128,2,4>",
+                              "k_d2q9_lattice<float,64,8,1>",  "k_d2q9_lattice<float,128,4,1>"};
   static const char* n64[] = {
       "k_d2q9_lattice<double,64,1,1>",  "k_d2q9_lattice<double,128,1,1>",
       "k_d2q9_lattice<double,256,1,1>", "k_d2q9_lattice<double,64,4,1>",
       "k_d2q9_lattice<double,128,2,1>", "k_d2q9_lattice<double,256,1,2>",
-      "k_d2q9_lattice<double,256,1,4>", "k_d2q9_lattice<double,128,2,4>"};
+      "k_d2q9_lattice<double,256,1,4>", "k_d2q9_lattice<double,128,2,4>",
+      "k_d2q9_lattice<double,64,8,1>",  "k_d2q9_lattice<double,128,4,1>"};
+  static_assert(sizeof(n32) / sizeof(n32[0]) == kNumLat2, "one name per variant");
+  static_assert(sizeof(n64) / sizeof(n64[0]) == kNumLat2, "one name per variant");
   if (v < 0 || v >= kNumLat2) return "?";
   return precision ? n32[v] : n64[v];
 }

@@ -52,3 +52,55 @@ def test_write_traffic_scales_by_the_copy_and_prices_plain_steps(tmp_path):
     assert abs(rec["ratio"] - 1.0) < 1e-12
     assert abs(out["k_step_lattice<float,256,1,1>"]["ratio"] - 1.5) < 1e-12
     assert rec["source_hash"] == bench.kernel_hash()
+
+
+def test_valu_summary_fractions(tmp_path):
+    # one dispatch of 1 ms at 2 GHz (GRBM_GUI_ACTIVE summed over 8 XCDs):
+    # half the VALU issue slots used, VALU busy a quarter of the time
+    cycles = 2.0e9 * 1e-3
+    name = "void rlb::(anonymous namespace)::k_step_tubes<float, 256, false>(rlb::TubeRound)"
+    fields = ["Dispatch_Id", "Grid_Size", "Workgroup_Size", "Kernel_Name", "Counter_Name",
+              "Counter_Value", "Start_Timestamp", "End_Timestamp"]
+    vals = {"SQ_INSTS_VALU": 0.5 * bench.CU_NUM * cycles,
+            "SQ_ACTIVE_INST_VALU": 0.25 * bench.CU_NUM * cycles,
+            "SQ_INSTS_LDS": 0.1 * bench.CU_NUM * cycles,
+            "GRBM_GUI_ACTIVE": bench.XCC_NUM * cycles}
+    with open(tmp_path / "c.csv", "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for c, v in vals.items():
+            w.writerow({"Dispatch_Id": 7, "Grid_Size": 65536, "Workgroup_Size": 256,
+                        "Kernel_Name": name, "Counter_Name": c, "Counter_Value": v,
+                        "Start_Timestamp": 1000, "End_Timestamp": 1000 + 1000000})
+    text = bench.valu_summary(str(tmp_path / "c.csv"), "cmd")
+    row = [l for l in text.splitlines() if l.startswith("| `k_step_tubes")]
+    assert len(row) == 1
+    cells = [c.strip() for c in row[0].split("|")[1:-1]]
+    assert cells[3] == "1" and cells[4] == "1000.0" and cells[5] == "2.00"
+    assert cells[7] == "0.500" and cells[8] == "0.250" and cells[9] == "0.200"
+
+
+def test_d2q9_traffic_names_both_corrected_kernels(tmp_path):
+    n = 64
+    cells = n * n
+    one = 2 * 18 * 4 * cells
+    kib = 1024.0
+    fetch = [(COPY, "131072", "FETCH_SIZE", (1 << 29) / kib)]
+    write = [(COPY, "131072", "WRITE_SIZE", (1 << 30) / kib)]
+    kern = {
+        "void rlb::(anonymous namespace)::k_d2q9_lattice<float, 128, 2, 1, false, true, false, "
+        "true>(...)": 1.0,
+        "void rlb::(anonymous namespace)::k_d2q9_lattice_c7<float, 64, 8, false, false, "
+        "true>(...)": 1.25,
+        "void rlb::(anonymous namespace)::k_d2q9_lattice_c7<float, 64, 8, true, false, "
+        "true>(...)": 9.0,  # fused diagnostics: not priced
+    }
+    for k, r in kern.items():
+        fetch.append((k, str(cells), "FETCH_SIZE", r * one / 2 / 2 / kib))
+        write.append((k, str(cells), "WRITE_SIZE", r * one / 2 / kib))
+    _write(tmp_path / "f.csv", fetch)
+    _write(tmp_path / "w.csv", write)
+    out = bench.d2q9_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), n=n)["kernels"]
+    assert sorted(out) == ["k_d2q9_lattice<float,128,2,1>+c7", "k_d2q9_lattice<float,64,8,1>+c7"]
+    assert abs(out["k_d2q9_lattice<float,128,2,1>+c7"]["ratio"] - 1.0) < 1e-12
+    assert abs(out["k_d2q9_lattice<float,64,8,1>+c7"]["ratio"] - 1.25) < 1e-12

@@ -237,8 +237,10 @@ def test_corrected_moderate_case_400_steps(prec, tol):
         assert err["f"] < tol and err["g"] < tol and err["u"] < tol and err["eps"] < tol, err
 
 
-@pytest.mark.parametrize("shape", [(160, 130, (0, 1, 0)), (45, 38, (1, 1, 0))],
-                         ids=["lattice", "persistent"])
+@pytest.mark.parametrize("shape", [(160, 130, (0, 1, 0)), (170, 131, (1, 0, 0)),
+                                   (140, 129, (0, 0, 0)), (45, 38, (1, 1, 0))],
+                         ids=["lattice", "lattice_ragged_y", "lattice_last_row_alone",
+                              "persistent"])
 def test_corrected_variants_identical(shape):
     import paper_1211_3286_amd as rlb
     prob = _problem(*shape)

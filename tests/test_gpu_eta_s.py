@@ -146,9 +146,10 @@ def test_tube_rounds_with_per_cell_taus(prec, tol):
 @pytest.mark.parametrize("corr", [0, 1], ids=["plain", "c7"])
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_d2q9_rounds_with_per_cell_taus(prec, corr):
-    """Strip rounds (a batch of narrow members) and tile rounds (one lattice)
-    with relaxation times from eta/s, with and without the correction term:
-    bit for bit the one-block / one-step kernels, which match the oracle."""
+    """Strip rounds (a batch of narrow members), tile rounds and every
+    one-step block shape (one lattice) with relaxation times from eta/s, with
+    and without the correction term: bit for bit the one-block / first
+    one-step kernels, which match the oracle."""
     members = [_random(4, 300, 1, (0, 1, 0), "d2q9", kappa=4 / 3),
                _random(3, 170, 1, (0, 0, 0), "d2q9", kappa=4 / 3)]
     for m in members:
@@ -159,6 +160,6 @@ def test_d2q9_rounds_with_per_cell_taus(prec, corr):
     lat.params.correction = corr
     big = lambda n: ",32,32>" in n or ",64,16>" in n
     ran = variants_equal_variant0(
-        [lat], prec, ("tiles",), 13, TOL[prec],
+        [lat], prec, ("tiles", "k_d2q9_lattice"), 13, TOL[prec],
         refused=lambda n: corr and (",64,8>" in n or (prec == FP64 and big(n))))
     assert len(ran) >= (1 if corr and prec == FP64 else 5)
