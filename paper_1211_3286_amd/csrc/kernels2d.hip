@@ -107,8 +107,11 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
 // them, keeping the recovery for its own collision; the block's first and
 // last valid rows also recover the rows beyond (their y-neighbours by the
 // y-streaming rule). A cell so costs 1 + 2/BY recoveries instead of the 3 of
-// k_d2q9_lattice with the correction, whose step is VALU-bound. Results are
-// those of k_d2q9_lattice bit for bit (the same fields from the same pulled g).
+// k_d2q9_lattice with the correction, whose step is VALU-bound. Tiles are
+// taken in the band order of block_tile_bands (the halo rows and the lines
+// shared with x-neighbours are L2 hits: 1.02x the algorithmic bytes instead of
+// 1.09-1.20x). Results are those of k_d2q9_lattice bit for bit (the same
+// fields from the same pulled g).
 // -------------------------------------------------------------------------
 template <typename T, int BX, int BY, bool DIAG, bool EXT, bool NTS>
 __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice_c7(const T* __restrict__ src,
@@ -120,8 +123,10 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice_c7(const T* __restrict_
   __shared__ int cok[R * BX];
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * BX + tx;
-  const int x = blockIdx.x * BX + tx;
-  const int y0 = blockIdx.y * BY;
+  int bx = blockIdx.x, by = blockIdx.y;
+  block_tile_bands(bx, by);
+  const int x = bx * BX + tx;
+  const int y0 = by * BY;
   const int rows = min(BY, geo.ny - y0);  // valid rows of the block (the grid makes it >= 1)
   const int y = y0 + ty;
   const bool xin = x < geo.nx;
@@ -321,6 +326,7 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int t = 0; t < a.nsteps; ++t) {
     T f[9], g[9];
+    d2q9::Recovered rec;  // with CORR: the recovery behind the published fields
     if (live) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
@@ -328,10 +334,8 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
         g[q] = lds[9 + q][slot[q]];
       }
       if constexpr (CORR) {
-        double gd[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) gd[q] = (double)g[q];
-        const d2q9::C7Fields F = d2q9::c7_fields_of(gd, d.ref);
+        rec = d2q9::recovered<T, EXT>(f, g, d.ref, &d.ext);
+        const d2q9::C7Fields F = d2q9::c7_fields(rec.mac, rec.ok);
         cf[0][w] = F.x1;
         cf[1][w] = F.gam;
         cf[2][w] = F.su2;
@@ -350,7 +354,11 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
         fp = d2q9::C7Fields{cf[0][sp], cf[1][sp], cf[2][sp], cf[3][sp], cok[sp] != 0};
       }
       Sums s;
-      const bool ok = d2q9::collide<T, CORR, EXT>(f, g, d.rt, d.ref, s, &fm, &fp, &d.ext);
+      bool ok;
+      if constexpr (CORR)
+        ok = d2q9::collide_recovered<T, true, EXT>(f, g, rec, d.rt, d.ref, s, &fm, &fp, &d.ext);
+      else
+        ok = d2q9::collide<T, false, EXT>(f, g, d.rt, d.ref, s, nullptr, nullptr, &d.ext);
       if (owned) {
         nbad += ok ? 0 : 1;
         if (diag)
@@ -491,6 +499,7 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
   for (int t = 0; t < a.nsteps; ++t) {
     // every pull of the step lands in registers before the in-place writes
     T f[CPT][9], g[CPT][9];
+    d2q9::Recovered rec[CPT];  // with CORR: the recoveries behind the published fields
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
       if (live[k]) {
@@ -500,10 +509,8 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
           g[k][q] = lds[9 + q][slot[k][q]];
         }
         if constexpr (CORR) {
-          double gd[9];
-#pragma unroll
-          for (int q = 0; q < 9; ++q) gd[q] = (double)g[k][q];
-          const d2q9::C7Fields F = d2q9::c7_fields_of(gd, a.ref);
+          rec[k] = d2q9::recovered<T, EXT>(f[k], g[k], a.ref, &a.ext);
+          const d2q9::C7Fields F = d2q9::c7_fields(rec[k].mac, rec[k].ok);
           const int c = tid + k * NTH;
           cf[0][c] = F.x1;
           cf[1][c] = F.gam;
@@ -530,8 +537,13 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
           fp = d2q9::C7Fields{cf[0][p], cf[1][p], cf[2][p], cf[3][p], cok[p] != 0};
         }
         Sums s;
-        const bool ok =
-            d2q9::collide<T, CORR, EXT>(f[k], g[k], a.rt, a.ref, s, &fm, &fp, &a.ext);
+        bool ok;
+        if constexpr (CORR)
+          ok = d2q9::collide_recovered<T, true, EXT>(f[k], g[k], rec[k], a.rt, a.ref, s, &fm,
+                                                     &fp, &a.ext);
+        else
+          ok = d2q9::collide<T, false, EXT>(f[k], g[k], a.rt, a.ref, s, nullptr, nullptr,
+                                            &a.ext);
         if (owned[k]) {
           nbad += ok ? 0 : 1;
           if (diag)
