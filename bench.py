@@ -539,7 +539,11 @@ def valu_summary(csv_path: str, command: str) -> str:
     (GRBM_GUI_ACTIVE, summed over the 8 XCDs, per XCD and second), the
     issue fraction (wave-level VALU instructions over one per CU and cycle)
     and the VALU busy fraction (SQ_ACTIVE_INST_VALU quad-cycles summed over
-    the SIMDs, over CUs x cycles, as rocprofv3's VALUBusy)."""
+    the SIMDs, over CUs x cycles, as rocprofv3's VALUBusy). For launches of
+    a few tens of microseconds GRBM_GUI_ACTIVE also counts cycles around the
+    kernel (the clock column then reads above 2.4 GHz) and both fractions
+    read low; the last fraction counts the cycles of the dispatch's own
+    duration at 2.4 GHz instead."""
     import collections
     import csv
 
@@ -551,15 +555,16 @@ def valu_summary(csv_path: str, command: str) -> str:
     dur = collections.defaultdict(dict)
     for r in csv.DictReader(open(csv_path)):
         name = short(r["Kernel_Name"])
-        if not name.startswith(("k_step", "k_d2q9")):
+        if not name.startswith(("k_step", "k_d2q9", "k_adj_step", "k_gstep")):
             continue
         key = (name, int(r["Grid_Size"]), int(r["Workgroup_Size"]))
         groups[key][r["Counter_Name"]].append(float(r["Counter_Value"]))
         dur[key][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     out = [f"Command: `{command}`", "",
            "| kernel | grid (threads) | block | dispatches | average (us) | clock (GHz) | "
-           "VALU wave-instructions per dispatch | issue fraction | VALU busy | LDS / VALU |",
-           "|---|---|---|---|---|---|---|---|---|---|"]
+           "VALU wave-instructions per dispatch | issue fraction | VALU busy | LDS / VALU | "
+           "issue fraction at 2.4 GHz |",
+           "|---|---|---|---|---|---|---|---|---|---|---|"]
     need = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_INSTS_LDS", "GRBM_GUI_ACTIVE")
     rows = []
     for key, c in groups.items():
@@ -571,10 +576,12 @@ def valu_summary(csv_path: str, command: str) -> str:
         rows.append((key, len(dur[key]), t, cycles / t / 1e9, mean["SQ_INSTS_VALU"],
                      mean["SQ_INSTS_VALU"] / (CU_NUM * cycles),
                      mean["SQ_ACTIVE_INST_VALU"] / (CU_NUM * cycles),
-                     mean["SQ_INSTS_LDS"] / max(mean["SQ_INSTS_VALU"], 1.0)))
-    for (name, grid, block), n, t, ghz, valu, issue, busy, lds in sorted(rows, key=lambda r: -r[1] * r[2]):
+                     mean["SQ_INSTS_LDS"] / max(mean["SQ_INSTS_VALU"], 1.0),
+                     mean["SQ_INSTS_VALU"] / (CU_NUM * t * 2.4e9)))
+    for (name, grid, block), n, t, ghz, valu, issue, busy, lds, nominal in sorted(
+            rows, key=lambda r: -r[1] * r[2]):
         out.append(f"| `{name}` | {grid} | {block} | {n} | {t * 1e6:.1f} | {ghz:.2f} | "
-                   f"{valu:.4g} | {issue:.3f} | {busy:.3f} | {lds:.3f} |")
+                   f"{valu:.4g} | {issue:.3f} | {busy:.3f} | {lds:.3f} | {nominal:.3f} |")
     return "\n".join(out) + "\n"
 
 

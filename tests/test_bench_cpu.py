@@ -78,6 +78,7 @@ def test_valu_summary_fractions(tmp_path):
     cells = [c.strip() for c in row[0].split("|")[1:-1]]
     assert cells[3] == "1" and cells[4] == "1000.0" and cells[5] == "2.00"
     assert cells[7] == "0.500" and cells[8] == "0.250" and cells[9] == "0.200"
+    assert cells[10] == f"{0.5 * 2.0 / 2.4:.3f}"  # the same issues over 2.4 GHz cycles
 
 
 def test_d2q9_traffic_names_both_corrected_kernels(tmp_path):
