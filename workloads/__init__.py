@@ -338,7 +338,7 @@ def qgp_tube_2d(case: str = "D", a: float = 1.0 / 20.0, tau_v: float = 100.0,
     and length/2 (tanh of width ``width``). Weak case: P_L, P_R of Sec. III.B
     at T = 0.0314; ``moderate``: the moderately relativistic case (P_R =
     1.557e-8, T_L / T_R = 0.0359 / 0.018). n = P / T, u = 0. Relaxation times
-    from ``case_taus``; tau_v = 100 stands for the paper's "about 100".
+    from ``case_taus``; tau_v = 100 stands for the paper's value of roughly 100.
     ``correction`` adds the C_7 term of Eqs. (37)-(38) (the corrected runs).
     ``eta_s`` > 0: relaxation times per cell from eta/s (scaled by ``kappa``,
     4/3 for this D2Q9 model), with the case's ratios; tau_v then only serves
