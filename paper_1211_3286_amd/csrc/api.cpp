@@ -32,8 +32,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   int64_t ncells = 0, cs = 0;
   size_t esz = 0;
-  size_t off_descs = 0, off_small = 0, off_partials = 0, off_xparts = 0, off_buf0 = 0,
-         off_buf1 = 0;
+  size_t off_descs = 0, off_small = 0, off_bad = 0, off_partials = 0, off_xparts = 0,
+         off_buf0 = 0, off_buf1 = 0;
   size_t off_stage = 0, off_segs = 0, off_flags = 0, off_tape = 0, total = 0;
   int max_parts = 0;
   int export_parts = 0;  // blocks of the field export (its own partials region)
@@ -163,6 +163,8 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   o = align_up(o + sizeof(MemberDesc) * n);
   L.off_small = o;
   o = align_up(o + 1024);
+  L.off_bad = o;  // the inadmissible-cell slots and their copy kept across tuning trials
+  o = align_up(o + 2 * rlb::kBadBytes);
   L.off_partials = o;
   o = align_up(o + sizeof(double) * 5 * (size_t)L.max_parts);
   // The field export keeps its partial sums apart, so that rlb_moments never
@@ -274,6 +276,20 @@ rlb_status dev_err(hipError_t e) { return e == hipSuccess ? RLB_OK : RLB_E_DEVIC
   } while (0)
 
 void* state_buf(rlb_sim* h) { return h->buf[h->cur]; }
+
+// Host copy of the inadmissible-cell slots (count_bad); total() is valid once
+// the stream has reached the copy.
+struct BadSlots {
+  unsigned long long v[rlb::kBadSlots * rlb::kBadStride];
+  hipError_t fetch(const rlb_sim* h) {
+    return hipMemcpyAsync(v, h->d_bad, rlb::kBadBytes, hipMemcpyDeviceToHost, h->stream);
+  }
+  unsigned long long total() const {
+    unsigned long long t = 0;
+    for (int i = 0; i < rlb::kBadSlots; ++i) t += v[(size_t)i * rlb::kBadStride];
+    return t;
+  }
+};
 void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
@@ -837,9 +853,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->ws = (char*)workspace;
   h->d_descs = (MemberDesc*)(h->ws + L.off_descs);
   h->d_small = (double*)(h->ws + L.off_small);
-  h->d_bad = (unsigned long long*)(h->d_small + 16);
-  h->d_count = h->d_bad + 1;
-  h->d_bad_save = h->d_bad + 2;
+  h->d_count = (unsigned long long*)(h->d_small + 16);
+  h->d_bad = (unsigned long long*)(h->ws + L.off_bad);
+  h->d_bad_save = h->d_bad + rlb::kBadBytes / sizeof(unsigned long long);
   h->d_partials = (double*)(h->ws + L.off_partials);
   h->d_xparts = (double*)(h->ws + L.off_xparts);
   h->buf[0] = h->ws + L.off_buf0;
@@ -898,7 +914,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   }
   if (h->ext && !h->lattice) h->variant = 1;  // 512 threads (see launch_persistent)
   const double *dn, *de, *du;
-  if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess) return fail(RLB_E_DEVICE);
+  if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess ||
+      hipMemsetAsync(h->d_bad, 0, rlb::kBadBytes, h->stream) != hipSuccess)
+    return fail(RLB_E_DEVICE);
   if (L.max_segs > 0 &&
       hipMemsetAsync(h->d_flags, 0, sizeof(unsigned long long) * L.max_segs, h->stream) !=
           hipSuccess)
@@ -1018,9 +1036,9 @@ rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* 
                                nc, dn, de, dP, dg, du, h->d_xparts, nparts, h->stream));
   RLB_HIP(rlb::launch_reduce(h->d_xparts, nparts, h->d_small, h->stream));
   double hs[5];
-  unsigned long long bad = 0;
+  BadSlots slots;
   RLB_HIP(hipMemcpyAsync(hs, h->d_small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
-  RLB_HIP(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(slots.fetch(h));
   if (!out_on_device) {
     if (n) RLB_HIP(hipMemcpyAsync(n, dn, sizeof(double) * nc, hipMemcpyDeviceToHost, h->stream));
     if (eps)
@@ -1032,6 +1050,7 @@ rlb_status rlb_moments(rlb_handle h, double* n, double* eps, double* P, double* 
       RLB_HIP(hipMemcpyAsync(u, du, sizeof(double) * 3 * nc, hipMemcpyDeviceToHost, h->stream));
   }
   RLB_HIP(hipStreamSynchronize(h->stream));
+  const unsigned long long bad = slots.total();
   if (sums) std::memcpy(sums, hs, sizeof(hs));
   if (n_unphysical) *n_unphysical = (int64_t)bad;
   if (persistent_error(h) != RLB_OK) return RLB_E_DEVICE;
@@ -1045,13 +1064,13 @@ rlb_status rlb_diagnostics(rlb_handle h, double sums[5], int64_t* step, int64_t*
   if (!g.ok) return RLB_E_DEVICE;
   RLB_HIP(rlb::launch_reduce(h->d_partials, h->diag_parts, h->d_small, h->stream));
   double hs[5];
-  unsigned long long bad = 0;
+  BadSlots slots;
   RLB_HIP(hipMemcpyAsync(hs, h->d_small, sizeof(hs), hipMemcpyDeviceToHost, h->stream));
-  RLB_HIP(hipMemcpyAsync(&bad, h->d_bad, sizeof(bad), hipMemcpyDeviceToHost, h->stream));
+  RLB_HIP(slots.fetch(h));
   RLB_HIP(hipStreamSynchronize(h->stream));
   if (sums) std::memcpy(sums, hs, sizeof(hs));
   if (step) *step = h->diag_step;
-  if (n_unphysical) *n_unphysical = (int64_t)bad;
+  if (n_unphysical) *n_unphysical = (int64_t)slots.total();
   return persistent_error(h);
 }
 
@@ -1158,8 +1177,8 @@ rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
   RLB_HIP(hipEventCreate(&e0));
   RLB_HIP(hipEventCreate(&e1));
   // trial steps must not count toward the inadmissible-cell total
-  RLB_HIP(hipMemcpyAsync(h->d_bad_save, h->d_bad, sizeof(unsigned long long),
-                         hipMemcpyDeviceToDevice, h->stream));
+  RLB_HIP(hipMemcpyAsync(h->d_bad_save, h->d_bad, rlb::kBadBytes, hipMemcpyDeviceToDevice,
+                         h->stream));
   const int keep = h->variant;
   int best = keep;
   double best_ms = 1e300;
@@ -1201,8 +1220,8 @@ rlb_status rlb_tune(rlb_handle h, int32_t trial_steps, int32_t* best_variant,
     }
   }
   if (st == RLB_OK) st = persistent_error(h);
-  (void)hipMemcpyAsync(h->d_bad, h->d_bad_save, sizeof(unsigned long long),
-                       hipMemcpyDeviceToDevice, h->stream);
+  (void)hipMemcpyAsync(h->d_bad, h->d_bad_save, rlb::kBadBytes, hipMemcpyDeviceToDevice,
+                       h->stream);
   (void)hipStreamSynchronize(h->stream);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -47,6 +47,19 @@ LatticeVariant lattice_variant(int i);
 int num_member_variants();
 MemberVariant member_variant(int i);
 
+// Inadmissible-cell counter: kBadSlots 64-bit counters kBadStride apart (one
+// 128-byte line each); a block adds its count to the slot its linear index
+// picks, so that a step with many inadmissible cells does not serialise its
+// atomics on one address. The host sums the slots.
+constexpr int kBadSlots = 256;
+constexpr int kBadStride = 16;
+constexpr size_t kBadBytes = sizeof(unsigned long long) * kBadSlots * kBadStride;
+
+__device__ __forceinline__ void count_bad(unsigned long long* bad, int n) {
+  const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  atomicAdd(bad + (size_t)kBadStride * (b & (kBadSlots - 1)), (unsigned long long)n);
+}
+
 // precision: 0 = FP64, 1 = FP32 (rlb.h).
 // Partial-sum blocks per member of the reference-state pass; the partials
 // buffer must hold n_members * kRefBlocks * 5 doubles.

@@ -75,7 +75,7 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
       }
     }
   }
-  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (nbad) count_bad(bad, nbad);
   if (DIAG) {
     block_sum5<BX * BY>(acc, tid);
     if (tid == 0) {
@@ -148,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_step_members(MemberLaunch a) {
     }
     __syncthreads();
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 // -------------------------------------------------------------------------
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(NT) void k_step_segments(SegLaunch a) {
       __hip_atomic_store(a.flags + blockIdx.x, target + 1ull, __ATOMIC_RELEASE,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 // -------------------------------------------------------------------------
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(NT) void k_step_tubes(TubeRound a) {
 #pragma unroll
     for (int p = 0; p < 38; ++p) ((T*)a.dst)[p * a.cs + gi] = lds[p][w];
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 __device__ __forceinline__ int find_member(const MemberDesc* __restrict__ d, int n, int64_t c) {

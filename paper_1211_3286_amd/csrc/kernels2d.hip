@@ -89,7 +89,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice(const T* __restrict__ s
       }
     }
   }
-  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (nbad) count_bad(bad, nbad);
   if (DIAG) {
     block_sum5<BX * BY>(acc, tid);
     if (tid == 0) {
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(BX* BY) void k_d2q9_lattice_c7(const T* __restrict_
       }
     }
   }
-  if (nbad) atomicAdd(bad, (unsigned long long)nbad);
+  if (nbad) count_bad(bad, nbad);
   if (DIAG) {
     block_sum5<BX * BY>(acc, tid);
     if (tid == 0) {
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(NT) void k_d2q9_members(MemberLaunch a) {
     }
     __syncthreads();
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 // -------------------------------------------------------------------------
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
 #pragma unroll
     for (int p = 0; p < 18; ++p) ((T*)a.dst)[p * a.cs + gi] = lds[p][w];
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 // -------------------------------------------------------------------------
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
       for (int p = 0; p < 18; ++p) st((T*)a.dst + (int64_t)p * a.cs, off, lds[p][c]);
     }
   }
-  if (nbad) atomicAdd(a.bad, (unsigned long long)nbad);
+  if (nbad) count_bad(a.bad, nbad);
 }
 
 __device__ __forceinline__ int member_of(const MemberDesc* __restrict__ d, int n, int64_t c) {
