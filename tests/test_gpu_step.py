@@ -204,3 +204,27 @@ def test_inadmissible_cells_counted_like_the_oracle():
     say("inadmissible: gpu", bad, "oracle", st.bad)
     assert bad == st.bad == 4
     assert relmax(gs["g"], st.g) < 1e-10 and relmax(gs["f"], st.f) < 1e-10
+
+
+@pytest.mark.gpu
+def test_inadmissible_count_over_many_blocks():
+    """The lattice kernels count inadmissible cells in 256 slots picked by the
+    block (one 128-byte line each) and the host sums them: on a 48^3 blast,
+    whose inadmissible cells fall in several hundred blocks, every block shape
+    gives the oracle's count (FP64)."""
+    import paper_1211_3286_amd as rlb
+    prob = wl.blast(48)
+    T = 3
+    st = oracle.run(prob, T)
+    assert st.bad > 50
+    sim = rlb.from_problems(prob, precision=FP64)
+    names = sim.variants()
+    sim.close()
+    for v, name in enumerate(names):
+        sim = rlb.from_problems(prob, precision=FP64)
+        sim.variant = v
+        sim.step(T)
+        _, _, bad = gpu_state(sim, prob)
+        say("  ", name, "gpu", bad, "oracle", st.bad)
+        assert bad == st.bad, name
+        sim.close()
