@@ -276,21 +276,23 @@ rlb_status dev_err(hipError_t e) { return e == hipSuccess ? RLB_OK : RLB_E_DEVIC
   } while (0)
 
 void* state_buf(rlb_sim* h) { return h->buf[h->cur]; }
+void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
-// Host copy of the inadmissible-cell slots (count_bad); total() is valid once
-// the stream has reached the copy.
+// Host copy of the inadmissible-cell slots (count_bad), one value per slot;
+// total() is valid once the stream has reached the copy.
 struct BadSlots {
-  unsigned long long v[rlb::kBadSlots * rlb::kBadStride];
+  unsigned long long v[rlb::kBadSlots];
   hipError_t fetch(const rlb_sim* h) {
-    return hipMemcpyAsync(v, h->d_bad, rlb::kBadBytes, hipMemcpyDeviceToHost, h->stream);
+    const size_t w = sizeof(unsigned long long);
+    return hipMemcpy2DAsync(v, w, h->d_bad, w * rlb::kBadStride, w, rlb::kBadSlots,
+                            hipMemcpyDeviceToHost, h->stream);
   }
   unsigned long long total() const {
     unsigned long long t = 0;
-    for (int i = 0; i < rlb::kBadSlots; ++i) t += v[(size_t)i * rlb::kBadStride];
+    for (int i = 0; i < rlb::kBadSlots; ++i) t += v[i];
     return t;
   }
 };
-void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
   if (h->d2)
