@@ -245,7 +245,8 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
     for prec, name, corr in ((rlb.FP32, "fp32", 0), (rlb.FP64, "fp64", 0),
                              (rlb.FP32, "fp32_c7", 1)):
         sim = rlb.from_problems(prob, precision=prec, diag_every=50, correction=corr)
-        tune = sim.tune(trial_steps=10)
+        # 30 trial steps: whole rounds for the tile variants of 2 and 3 steps
+        tune = sim.tune(trial_steps=30)
         s0 = sim.sums()
         ms, _ = time_steps(torch, sim, steps, warmup)
         s1 = sim.sums()

@@ -401,12 +401,12 @@ __global__ __launch_bounds__(NT) void k_d2q9_strips(TubeRound a) {
 // an axis no longer than the block is one whole window, wrapped if periodic.
 // The step itself is that of k_d2q9_strips (pull from LDS, C_7 fields
 // published in LDS, collide in registers, write back in place), and gives the
-// same results as the one-step kernels bit for bit. Without the correction
-// term, step t + 1 of a round updates only the window less t + 1 cells at each
-// halo edge (the owned cells need no more), its cells dealt to the threads
-// row by row so that whole waves drop out. The owned cells are
-// written with plain stores: on 4096^2 lattices (2.4 GB FP32 state) that
-// measured 7 % faster per step than nontemporal stores in FP32 and 1 % in
+// same results as the one-step kernels bit for bit. Step t + 1 of a round
+// updates only the window less t + 1 cells (2(t + 1) rows in y with the
+// correction) at each halo edge, which is all the owned cells need, its cells
+// dealt to the threads row by row so that whole waves drop out. The owned
+// cells are written with plain stores: on 4096^2 lattices (2.4 GB FP32 state)
+// that measured 7 % faster per step than nontemporal stores in FP32 and 1 % in
 // FP64, as the next round's halo reads of freshly written cells hit in cache.
 // -------------------------------------------------------------------------
 struct AxisWindow {
@@ -445,6 +445,7 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
   constexpr int NT = TX * TY;     // window cells
   constexpr int CPT = NT / NTH;   // window cells per thread: c = tid + k * NTH
   static_assert(CPT * NTH == NT, "threads must divide the window");
+  constexpr int YS = CORR ? 2 : 1;  // halo rows consumed per step along y
   __shared__ T lds[18][NT];
   __shared__ double cf[CORR ? 4 : 1][CORR ? NT : 1];  // x1, gamma, sigma u^2, sigma u
   __shared__ int cok[CORR ? NT : 1];
@@ -453,15 +454,14 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
   const AxisWindow X = axis_window(bx, a.nx, TX, a.ox, a.hx, a.bcx);
   const AxisWindow Y = axis_window(by, a.ny, TY, a.oy, a.hy, a.bcy);
   const int tid = threadIdx.x;
-  bool live[CPT], owned[CPT];
+  bool owned[CPT];
   int64_t gi[CPT];
-  int slot[CPT][9], sm[CPT], sp[CPT];
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int c = tid + k * NTH;
     const int i = c % TX, j = c / TX;
-    live[k] = i < X.wlen && j < Y.wlen;
-    owned[k] = live[k] && X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
+    const bool live = i < X.wlen && j < Y.wlen;
+    owned[k] = live && X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
                Y.w0 + j < Y.own1;
     int gx = X.w0 + i, gy = Y.w0 + j;
     if (gx < 0) gx += a.nx;
@@ -469,136 +469,68 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
     if (gy < 0) gy += a.ny;
     if (gy >= a.ny) gy -= a.ny;
     gi[k] = (int64_t)gy * a.nx + gx;
-    if (live[k]) {
+    if (live) {
 #pragma unroll
       for (int p = 0; p < 18; ++p) lds[p][c] = ((const T*)a.src)[p * a.cs + gi[k]];
-    }
-    if constexpr (!CORR) continue;  // the steps below map their cells themselves
-    int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-    if (im < 0) im = X.left == kEdgeWrap ? X.wlen - 1 : 0;
-    if (ip >= X.wlen) ip = X.right == kEdgeWrap ? 0 : X.wlen - 1;
-    if (jm < 0) jm = Y.left == kEdgeWrap ? Y.wlen - 1 : 0;
-    if (jp >= Y.wlen) jp = Y.right == kEdgeWrap ? 0 : Y.wlen - 1;
-    // pull source of velocity a: the cell at (i, j) - e_a
-    slot[k][0] = j * TX + i;
-    slot[k][1] = j * TX + im;
-    slot[k][2] = jm * TX + i;
-    slot[k][3] = j * TX + ip;
-    slot[k][4] = jp * TX + i;
-    slot[k][5] = jm * TX + im;
-    slot[k][6] = jm * TX + ip;
-    slot[k][7] = jp * TX + ip;
-    slot[k][8] = jp * TX + im;
-    sm[k] = jm * TX + i;  // C_7 neighbours
-    sp[k] = jp * TX + i;
-    if (!live[k]) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) slot[k][q] = 0;
-      sm[k] = sp[k] = 0;
     }
   }
   __syncthreads();
   int nbad = 0;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if constexpr (!CORR) {
-    for (int t = 0; t < a.nsteps; ++t) {
-      // Step t + 1 updates the window less t + 1 cells at each halo edge:
-      // the owned cells after the round depend on no cell beyond that. The
-      // region's cells are dealt to the threads row by row (r = tid + k NTH),
-      // so whole waves drop out as it shrinks.
-      const int s = t + 1;
-      const int i0 = X.left == kEdgeHalo ? s : 0;
-      const int i1 = X.wlen - (X.right == kEdgeHalo ? s : 0);
-      const int j0 = Y.left == kEdgeHalo ? s : 0;
-      const int j1 = Y.wlen - (Y.right == kEdgeHalo ? s : 0);
-      const int w = i1 - i0, n = w * (j1 - j0);
-      T f[CPT][9], g[CPT][9];
-      int cell[CPT];
-      bool own[CPT];
-#pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        const int r = tid + k * NTH;
-        cell[k] = -1;
-        own[k] = false;
-        if (r < n) {
-          const int jr = r / w;
-          const int i = i0 + (r - jr * w), j = j0 + jr;
-          int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
-          if (im < 0) im = X.left == kEdgeWrap ? X.wlen - 1 : 0;
-          if (ip >= X.wlen) ip = X.right == kEdgeWrap ? 0 : X.wlen - 1;
-          if (jm < 0) jm = Y.left == kEdgeWrap ? Y.wlen - 1 : 0;
-          if (jp >= Y.wlen) jp = Y.right == kEdgeWrap ? 0 : Y.wlen - 1;
-          // pull source of velocity a: the cell at (i, j) - e_a
-          const int sl[9] = {j * TX + i,   j * TX + im,  jm * TX + i,  j * TX + ip, jp * TX + i,
-                             jm * TX + im, jm * TX + ip, jp * TX + ip, jp * TX + im};
-#pragma unroll
-          for (int q = 0; q < 9; ++q) {
-            f[k][q] = lds[q][sl[q]];
-            g[k][q] = lds[9 + q][sl[q]];
-          }
-          cell[k] = j * TX + i;
-          own[k] = X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
-                   Y.w0 + j < Y.own1;
-        }
-      }
-      __syncthreads();
-      const int64_t sidx = a.step0 + t + 1;
-      const bool diag =
-          a.diag_every > 0 && ((sidx % a.diag_every) == 0 || sidx == a.last_step);
-      if (diag)
-#pragma unroll
-        for (int q = 0; q < 5; ++q) acc[q] = 0.0;
-#pragma unroll
-      for (int k = 0; k < CPT; ++k) {
-        if (cell[k] >= 0) {
-          Sums sm5;
-          const bool ok = d2q9::collide<T, false, EXT>(f[k], g[k], a.rt, a.ref, sm5, nullptr,
-                                                       nullptr, &a.ext);
-          if (own[k]) {
-            nbad += ok ? 0 : 1;
-            if (diag)
-#pragma unroll
-              for (int q = 0; q < 5; ++q) acc[q] += sm5.v[q];
-          }
-#pragma unroll
-          for (int q = 0; q < 9; ++q) {
-            lds[q][cell[k]] = f[k][q];
-            lds[9 + q][cell[k]] = g[k][q];
-          }
-        }
-      }
-      if (diag) {
-        block_sum5<NTH>(acc, tid);
-        if (tid == 0) {
-          const int64_t b = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) a.partials[b * 5 + q] = acc[q];
-        }
-      }
-      __syncthreads();
-    }
-  } else {
   for (int t = 0; t < a.nsteps; ++t) {
+    // Step s = t + 1 updates the window less s cells (YS s rows) at each halo
+    // edge: the owned cells after the round need no more. With the correction
+    // the cells one row further out also publish their C_7 fields, which their
+    // y-neighbours in the region read. The cells are dealt to the threads row
+    // by row (r = tid + k NTH), so whole waves drop out as the region shrinks.
+    const int s = t + 1;
+    const int i0 = X.left == kEdgeHalo ? s : 0;
+    const int i1 = X.wlen - (X.right == kEdgeHalo ? s : 0);
+    const int j0 = Y.left == kEdgeHalo ? YS * s : 0;
+    const int j1 = Y.wlen - (Y.right == kEdgeHalo ? YS * s : 0);
+    const int pj0 = CORR && Y.left == kEdgeHalo ? j0 - 1 : j0;
+    const int pj1 = CORR && Y.right == kEdgeHalo ? j1 + 1 : j1;
+    const int w = i1 - i0, n = w * (pj1 - pj0);
     // every pull of the step lands in registers before the in-place writes
     T f[CPT][9], g[CPT][9];
-    d2q9::Recovered rec[CPT];  // with CORR: the recoveries behind the published fields
+    d2q9::Recovered rec[CPT];  // with CORR: the recovery behind the published fields
+    int cell[CPT], cm[CPT], cp[CPT];
+    bool upd[CPT], own[CPT];
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-      if (live[k]) {
+      const int r = tid + k * NTH;
+      cell[k] = cm[k] = cp[k] = 0;
+      upd[k] = own[k] = false;
+      if (r < n) {
+        const int jr = r / w;
+        const int i = i0 + (r - jr * w), j = pj0 + jr;
+        int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
+        if (im < 0) im = X.left == kEdgeWrap ? X.wlen - 1 : 0;
+        if (ip >= X.wlen) ip = X.right == kEdgeWrap ? 0 : X.wlen - 1;
+        if (jm < 0) jm = Y.left == kEdgeWrap ? Y.wlen - 1 : 0;
+        if (jp >= Y.wlen) jp = Y.right == kEdgeWrap ? 0 : Y.wlen - 1;
+        // pull source of velocity a: the cell at (i, j) - e_a
+        const int sl[9] = {j * TX + i,   j * TX + im,  jm * TX + i,  j * TX + ip, jp * TX + i,
+                           jm * TX + im, jm * TX + ip, jp * TX + ip, jp * TX + im};
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          f[k][q] = lds[q][slot[k][q]];
-          g[k][q] = lds[9 + q][slot[k][q]];
+          f[k][q] = lds[q][sl[q]];
+          g[k][q] = lds[9 + q][sl[q]];
         }
+        cell[k] = j * TX + i;
+        cm[k] = jm * TX + i;  // C_7 neighbours
+        cp[k] = jp * TX + i;
+        upd[k] = j >= j0 && j < j1;
+        own[k] = X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
+                 Y.w0 + j < Y.own1;
         if constexpr (CORR) {
           rec[k] = d2q9::recovered<T, EXT>(f[k], g[k], a.ref, &a.ext);
           const d2q9::C7Fields F = d2q9::c7_fields(rec[k].mac, rec[k].ok);
-          const int c = tid + k * NTH;
-          cf[0][c] = F.x1;
-          cf[1][c] = F.gam;
-          cf[2][c] = F.su2;
-          cf[3][c] = F.su;
-          cok[c] = F.ok ? 1 : 0;
+          cf[0][cell[k]] = F.x1;
+          cf[1][cell[k]] = F.gam;
+          cf[2][cell[k]] = F.su2;
+          cf[3][cell[k]] = F.su;
+          cok[cell[k]] = F.ok ? 1 : 0;
         }
       }
     }
@@ -611,32 +543,29 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
       for (int q = 0; q < 5; ++q) acc[q] = 0.0;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
-      if (live[k]) {
-        d2q9::C7Fields fm, fp;
-        if constexpr (CORR) {
-          const int m = sm[k], p = sp[k];
-          fm = d2q9::C7Fields{cf[0][m], cf[1][m], cf[2][m], cf[3][m], cok[m] != 0};
-          fp = d2q9::C7Fields{cf[0][p], cf[1][p], cf[2][p], cf[3][p], cok[p] != 0};
-        }
-        Sums s;
+      if (upd[k]) {
+        Sums sm5;
         bool ok;
-        if constexpr (CORR)
-          ok = d2q9::collide_recovered<T, true, EXT>(f[k], g[k], rec[k], a.rt, a.ref, s, &fm,
+        if constexpr (CORR) {
+          const int m = cm[k], p = cp[k];
+          const d2q9::C7Fields fm{cf[0][m], cf[1][m], cf[2][m], cf[3][m], cok[m] != 0};
+          const d2q9::C7Fields fp{cf[0][p], cf[1][p], cf[2][p], cf[3][p], cok[p] != 0};
+          ok = d2q9::collide_recovered<T, true, EXT>(f[k], g[k], rec[k], a.rt, a.ref, sm5, &fm,
                                                      &fp, &a.ext);
-        else
-          ok = d2q9::collide<T, false, EXT>(f[k], g[k], a.rt, a.ref, s, nullptr, nullptr,
+        } else {
+          ok = d2q9::collide<T, false, EXT>(f[k], g[k], a.rt, a.ref, sm5, nullptr, nullptr,
                                             &a.ext);
-        if (owned[k]) {
+        }
+        if (own[k]) {
           nbad += ok ? 0 : 1;
           if (diag)
 #pragma unroll
-            for (int q = 0; q < 5; ++q) acc[q] += s.v[q];
+            for (int q = 0; q < 5; ++q) acc[q] += sm5.v[q];
         }
-        const int c = tid + k * NTH;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          lds[q][c] = f[k][q];
-          lds[9 + q][c] = g[k][q];
+          lds[q][cell[k]] = f[k][q];
+          lds[9 + q][cell[k]] = g[k][q];
         }
       }
     }
@@ -649,7 +578,6 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
       }
     }
     __syncthreads();
-  }
   }
 #pragma unroll
   for (int k = 0; k < CPT; ++k) {
