@@ -225,6 +225,7 @@ struct rlb_sim {
   double* d_small = nullptr;  // [0..4] sums out, [8..] scratch
   unsigned long long* d_bad = nullptr;
   unsigned long long* d_count = nullptr;
+  unsigned long long* d_bad_total = nullptr;  // the slots' total for the host
   unsigned long long* d_bad_save = nullptr;
   double* d_partials = nullptr;
   double* d_xparts = nullptr;  // export partials (rlb_moments)
@@ -278,20 +279,16 @@ rlb_status dev_err(hipError_t e) { return e == hipSuccess ? RLB_OK : RLB_E_DEVIC
 void* state_buf(rlb_sim* h) { return h->buf[h->cur]; }
 void* spare_buf(rlb_sim* h) { return h->buf[1 - h->cur]; }
 
-// Host copy of the inadmissible-cell slots (count_bad), one value per slot;
-// total() is valid once the stream has reached the copy.
+// Total of the inadmissible-cell slots (count_bad), summed on the device and
+// copied back; total() is valid once the stream has reached the copy.
 struct BadSlots {
-  unsigned long long v[rlb::kBadSlots];
+  unsigned long long v = 0;
   hipError_t fetch(const rlb_sim* h) {
-    const size_t w = sizeof(unsigned long long);
-    return hipMemcpy2DAsync(v, w, h->d_bad, w * rlb::kBadStride, w, rlb::kBadSlots,
-                            hipMemcpyDeviceToHost, h->stream);
+    hipError_t e = rlb::launch_sum_bad(h->d_bad, h->d_bad_total, h->stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(&v, h->d_bad_total, sizeof(v), hipMemcpyDeviceToHost, h->stream);
   }
-  unsigned long long total() const {
-    unsigned long long t = 0;
-    for (int i = 0; i < rlb::kBadSlots; ++i) t += v[i];
-    return t;
-  }
+  unsigned long long total() const { return v; }
 };
 
 rlb_status launch_lattice_step(rlb_sim* h, int variant, bool diag, const void* src, void* dst) {
@@ -856,6 +853,7 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->d_descs = (MemberDesc*)(h->ws + L.off_descs);
   h->d_small = (double*)(h->ws + L.off_small);
   h->d_count = (unsigned long long*)(h->d_small + 16);
+  h->d_bad_total = (unsigned long long*)(h->d_small + 20);
   h->d_bad = (unsigned long long*)(h->ws + L.off_bad);
   h->d_bad_save = h->d_bad + rlb::kBadBytes / sizeof(unsigned long long);
   h->d_partials = (double*)(h->ws + L.off_partials);

@@ -170,6 +170,9 @@ hipError_t launch_population_planes(int precision, const void* state, int64_t cs
                                     const MemberDesc* descs, int n_members, int64_t ncells,
                                     int p0, int np, double* out, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int nparts, double* out5, hipStream_t s);
+// The total of the inadmissible-cell slots into *out (device).
+hipError_t launch_sum_bad(const unsigned long long* slots, unsigned long long* out,
+                          hipStream_t s);
 const char* lattice_kernel_name(int precision, int variant);
 const char* member_kernel_name(int precision, int variant);
 

@@ -585,6 +585,20 @@ const void* mem_func(int v) {
   return nullptr;
 }
 
+// Total of the inadmissible-cell slots (count_bad) into *out: one block of
+// kBadSlots threads.
+__global__ __launch_bounds__(kBadSlots) void k_sum_bad(const unsigned long long* __restrict__ slots,
+                                                        unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long sh[kBadSlots];
+  sh[threadIdx.x] = slots[(size_t)threadIdx.x * kBadStride];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int k = 0; k < kBadSlots; ++k) t += sh[k];
+    *out = t;
+  }
+}
+
 }  // namespace
 
 int num_lattice_variants() { return kNumLat; }
@@ -755,6 +769,12 @@ hipError_t launch_population_planes(int precision, const void* state, int64_t cs
 
 hipError_t launch_reduce(const double* partials, int nparts, double* out5, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, partials, nparts, out5);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_bad(const unsigned long long* slots, unsigned long long* out,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_bad, dim3(1), dim3(kBadSlots), 0, s, slots, out);
   return hipGetLastError();
 }
 
