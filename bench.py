@@ -259,8 +259,15 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
         tiles = tile_traffic(tune["name"], n, n, bpc // 2, corr)
         if tiles:
             # tile rounds move fewer bytes than one step's 2 x 18 values per
-            # cell update; achieved_gbs above is the one-step equivalent
+            # cell update: bytes_per_cell, achieved_gbs and frac count the
+            # round's own traffic (window read + owned write per H steps), and
+            # the one-step equivalent is kept beside them
             tiles["hbm_gbs"] = tiles["hbm_bytes_per_cell_update"] * cells / (ms * 1e-3) / 1e9
+            out[name].update({"bytes_per_cell": tiles["hbm_bytes_per_cell_update"],
+                              "achieved_gbs": tiles["hbm_gbs"],
+                              "frac": tiles["hbm_gbs"] / HBM_PEAK_GBS,
+                              "one_step_equivalent_gbs": gbs,
+                              "one_step_equivalent_frac": gbs / HBM_PEAK_GBS})
             out[name]["tile_rounds"] = tiles
         sim.close()
     del prob
