@@ -51,26 +51,71 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
       uint32_t off[19], self;
       pull_offsets(x, y, z, geo.nx, geo.ny, geo.nz, geo.bcx, geo.bcy, geo.bcz, 0u, esz, off,
                    self);
-      T f[19], g[19];
+      if constexpr (!EXT && sizeof(T) == 8) {
+        // FP64: g first (its recovery needs no f), then f with the recovered
+        // velocity, so that only one distribution's 19 doubles are live at a
+        // time (142 instead of 154 VGPRs; 1.5 % faster). The arithmetic is
+        // that of collide(), bit for bit.
+        T g[19];
 #pragma unroll
-      for (int a = 0; a < 19; ++a) {
-        f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
-        g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
-      }
-      Sums s;
-      const bool ok = collide<T, EXT>(f, g, geo.rt, geo.ref, s, &geo.ext);
-      nbad += ok ? 0 : 1;
-      if (DIAG)
+        for (int a = 0; a < 19; ++a) g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
+        double E, Mx, My, Mz, gs;
+        g_sums(g, geo.ref, E, Mx, My, Mz, gs);
+        Macro mac;
+        const bool ok = recover(E, Mx, My, Mz, mac);
+        if (ok) collide_g(g, Mx, My, Mz, gs, mac, geo.rt, geo.ref);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+        for (int a = 0; a < 19; ++a) {
+          if constexpr (NTS)
+            st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+          else
+            st(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+        }
+        T f[19];
 #pragma unroll
-      for (int a = 0; a < 19; ++a) {
-        if constexpr (NTS) {
-          st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
-          st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
-        } else {
-          st(dst + (int64_t)a * geo.cs, self, f[a]);
-          st(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+        for (int a = 0; a < 19; ++a) f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
+        double fs = 0.0;
+#pragma unroll
+        for (int a = 0; a < 19; ++a) fs += (double)f[a];
+        const double N = geo.ref.n + fs;
+        if (ok) collide_f(f, N, fs, mac, geo.rt, geo.ref);
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+          if constexpr (NTS)
+            st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+          else
+            st(dst + (int64_t)a * geo.cs, self, f[a]);
+        }
+        nbad += ok ? 0 : 1;
+        if (DIAG) {
+          acc[0] += N;
+          acc[1] += E;
+          acc[2] += Mx;
+          acc[3] += My;
+          acc[4] += Mz;
+        }
+      } else {
+        T f[19], g[19];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+          f[a] = ld(src + (int64_t)a * geo.cs, off[a]);
+          g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
+        }
+        Sums s;
+        const bool ok = collide<T, EXT>(f, g, geo.rt, geo.ref, s, &geo.ext);
+        nbad += ok ? 0 : 1;
+        if (DIAG)
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i] += s.v[i];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) {
+          if constexpr (NTS) {
+            st_nt(dst + (int64_t)a * geo.cs, self, f[a]);
+            st_nt(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+          } else {
+            st(dst + (int64_t)a * geo.cs, self, f[a]);
+            st(dst + (int64_t)(19 + a) * geo.cs, self, g[a]);
+          }
         }
       }
     }
