@@ -193,3 +193,52 @@ def test_open_ends_keep_far_field(orc):
     assert np.abs(res[1][:20] - eps0.eps[:20, 0, 0]).max() < 1e-12
     assert np.abs(res[1][-20:] - eps0.eps[-20:, 0, 0]).max() < 1e-12
     assert np.abs(res[0][:20] - eps0.eps[:20, 0, 0]).max() > 1e-3
+
+
+# Non-hydrodynamic modes of g over whole runs: on a uniform periodic lattice
+# streaming maps every population onto an equal one, and the conserved sums
+# (hence the equilibria) do not change, so a perturbation along one moment row
+# decays by (1 - 1/tau) per step, tau the rate Eq. (31) gives that row. The
+# rows are written here from their closed forms in |e|^2 (the bulk row
+# e = 19 r^2 - 30 (D3Q19), 3 r^2 - 4 (D2Q9) with tau_e; the energy-square row
+# (21 r^4 - 53 r^2 + 24)/2, (9 r^4 - 21 r^2 + 8)/2 with tau_eps), not taken
+# from the oracle's basis, so a wrong row, norm or rate mapping breaks the
+# single-exponential decay.
+_ROWS = {
+    ("d3q19", "e"): (lambda r2: 19.0 * r2 - 30.0, "tau_e"),
+    ("d3q19", "eps"): (lambda r2: (21.0 * r2 * r2 - 53.0 * r2 + 24.0) / 2.0, "tau_eps"),
+    ("d2q9", "e"): (lambda r2: 3.0 * r2 - 4.0, "tau_e"),
+    ("d2q9", "eps"): (lambda r2: (9.0 * r2 * r2 - 21.0 * r2 + 8.0) / 2.0, "tau_eps"),
+}
+
+
+@pytest.mark.parametrize("lattice,row", list(_ROWS), ids=lambda v: str(v))
+def test_ghost_mode_decays_at_its_rate(lattice, row):
+    import oracle
+    taus = dict(tau_f=0.7, tau_v=0.8, tau_e=0.6, tau_eps=1.3, tau_q=1.1)
+    if lattice == "d2q9":
+        prob = wl.uniform(4, 5, 1, n=1.0, eps=1.0, u=(0.12, -0.07, 0.0), **taus)
+        prob.params.lattice = "d2q9"
+        e = oracle.d2q9_tables()["e"]
+    else:
+        prob = wl.uniform(4, 5, 3, n=1.0, eps=1.0, u=(0.12, -0.07, 0.05), **taus)
+        e = oracle.tables()["e"]
+    poly, rate = _ROWS[(lattice, row)]
+    r2 = (np.asarray(e, dtype=float) ** 2).sum(axis=1)
+    phi = poly(r2)
+    delta = 1e-3
+    base = oracle.State.init(prob)
+    pert = oracle.State.init(prob)
+    pert.g += (delta * phi / (phi * phi).sum())[:, None, None, None]
+    T = 12
+    base.step(T)
+    pert.step(T)
+    m = np.tensordot(phi, pert.g - base.g, axes=1)  # the row's moment in every cell
+    expect = delta * (1.0 - 1.0 / taus[rate]) ** T
+    assert np.abs(m - expect).max() < 1e-9 * abs(delta)
+    # the perturbation stays in that row: the other moments of the difference
+    # (here the plain sum and the other ghost row) stay at rounding level
+    assert np.abs((pert.g - base.g).sum(axis=0)).max() < 1e-10 * delta
+    other = [k for k in _ROWS if k[0] == lattice and k[1] != row][0]
+    phi2 = _ROWS[other][0](r2)
+    assert np.abs(np.tensordot(phi2, pert.g - base.g, axes=1)).max() < 1e-10 * delta
