@@ -773,7 +773,7 @@ const void* mem2_func(int v) {
 
 // tile rounds: block (= window) shape and steps per launch
 constexpr TileVariant kTile2[] = {{32, 16, 2}, {64, 8, 2}, {32, 32, 2}, {64, 16, 2}, {32, 32, 3},
-                                  {64, 16, 3}};
+                                  {64, 16, 3}, {32, 16, 3}};
 constexpr int kNumTile2 = sizeof(kTile2) / sizeof(kTile2[0]);
 
 // LDS of a tile block: the window's 18 populations, and with the correction
@@ -805,6 +805,7 @@ hipError_t tile2_dispatch(int v, const TileRound& a, dim3 grid, hipStream_t s) {
     case 3: return tile2_launch<T, 64, 16, CORR, EXT>(a, grid, s);
     case 4: return tile2_launch<T, 32, 32, CORR, EXT>(a, grid, s);
     case 5: return tile2_launch<T, 64, 16, CORR, EXT>(a, grid, s);
+    case 6: return tile2_launch<T, 32, 16, CORR, EXT>(a, grid, s);
   }
   return hipErrorInvalidValue;
 }
@@ -919,10 +920,14 @@ hipError_t d2q9_launch_tiles(int precision, int v, bool corr, bool ext, const Ti
 const char* d2q9_tile_kernel_name(int precision, int v) {
   static const char* n32[] = {"k_d2q9_tiles<float,32,16>/h2", "k_d2q9_tiles<float,64,8>/h2",
                               "k_d2q9_tiles<float,32,32>/h2", "k_d2q9_tiles<float,64,16>/h2",
-                              "k_d2q9_tiles<float,32,32>/h3", "k_d2q9_tiles<float,64,16>/h3"};
+                              "k_d2q9_tiles<float,32,32>/h3", "k_d2q9_tiles<float,64,16>/h3",
+                              "k_d2q9_tiles<float,32,16>/h3"};
   static const char* n64[] = {"k_d2q9_tiles<double,32,16>/h2", "k_d2q9_tiles<double,64,8>/h2",
                               "k_d2q9_tiles<double,32,32>/h2", "k_d2q9_tiles<double,64,16>/h2",
-                              "k_d2q9_tiles<double,32,32>/h3", "k_d2q9_tiles<double,64,16>/h3"};
+                              "k_d2q9_tiles<double,32,32>/h3", "k_d2q9_tiles<double,64,16>/h3",
+                              "k_d2q9_tiles<double,32,16>/h3"};
+  static_assert(sizeof(n32) / sizeof(n32[0]) == kNumTile2, "one name per variant");
+  static_assert(sizeof(n64) / sizeof(n64[0]) == kNumTile2, "one name per variant");
   if (v < 0 || v >= kNumTile2) return "?";
   return precision ? n32[v] : n64[v];
 }
