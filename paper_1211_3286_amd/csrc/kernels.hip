@@ -51,11 +51,15 @@ __global__ __launch_bounds__(BX* BY) void k_step_lattice(const T* __restrict__ s
       uint32_t off[19], self;
       pull_offsets(x, y, z, geo.nx, geo.ny, geo.nz, geo.bcx, geo.bcy, geo.bcz, 0u, esz, off,
                    self);
-      if constexpr (!EXT && sizeof(T) == 8) {
-        // FP64: g first (its recovery needs no f), then f with the recovered
-        // velocity, so that only one distribution's 19 doubles are live at a
-        // time (142 instead of 154 VGPRs; 1.5 % faster). The arithmetic is
-        // that of collide(), bit for bit.
+      if constexpr (!EXT && (sizeof(T) == 8 || CZ == 1)) {
+        // g first (its recovery needs no f), then f with the recovered
+        // velocity: one distribution's 19 values in flight at a time. FP64:
+        // 142 instead of 154 VGPRs, 1.5 % faster; FP32 with one cell per
+        // thread: 0.3-0.5 % faster (with several cells per thread FP32 lost
+        // 2-9 %, and loads both at once). The arithmetic is that of collide(),
+        // bit for bit. (The relaxation times from eta/s and the general
+        // equation of state need N before the recovery, so the EXT kernels
+        // load both at once.)
         T g[19];
 #pragma unroll
         for (int a = 0; a < 19; ++a) g[a] = ld(src + (int64_t)(19 + a) * geo.cs, off[a]);
