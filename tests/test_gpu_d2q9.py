@@ -439,3 +439,41 @@ def test_tile_rounds_with_per_cell_taus(prec):
             f, g = [t.cpu().numpy() for t in s2.populations()]
             assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1]), name
             s2.close()
+
+
+@pytest.mark.parametrize("corr", [0, 1], ids=["plain", "c7"])
+@pytest.mark.parametrize("L", [136, 100], ids=["lattice", "persistent"])
+def test_inadmissible_cells_counted_like_the_oracle(L, corr):
+    """A 2D blast whose outward ring turns cells inadmissible (E <= 0 or
+    |M| >= E) within a few steps: every variant of both dispatch paths (one-step
+    lattice kernels, tile rounds, per-member and strip rounds), with and
+    without the correction term, leaves those cells uncollided and counts them
+    like the oracle (FP64 decisions). Next to near-vacuum cells rounding
+    differences are amplified, hence the looser population bound."""
+    import paper_1211_3286_amd as rlb
+    prob = wl.blast_disk(L, correction=corr)
+    T = 4
+    st = oracle.run(prob, T)
+    assert st.bad > 50
+    sim = rlb.from_problems(prob, precision=FP64)
+    names = sim.variants()
+    sim.close()
+    ran = 0
+    for v, name in enumerate(names):
+        sim = rlb.from_problems(prob, precision=FP64)
+        sim.variant = v
+        try:
+            sim.step(T)
+        except rlb.RLBError as e:
+            # FP64 tile windows of 1024 cells with the correction term do not
+            # fit LDS; strip rounds refuse members wider than a strip
+            assert e.code == -7 and ((corr and "tiles" in name) or "strips" in name), name
+            sim.close()
+            continue
+        (gs,), _, bad = gpu_state(sim, prob)
+        say("  disk", L, "corr", corr, name, "gpu", bad, "oracle", st.bad)
+        assert bad == st.bad, name
+        assert relmax(gs["f"], st.f) < 1e-10 and relmax(gs["g"], st.g) < 1e-10, name
+        ran += 1
+        sim.close()
+    assert ran >= 2

@@ -22,6 +22,7 @@ problem class the model was built for):
 ``tube_batch``     64 ragged shock tubes with per-tube relaxation times.
 ``shear_vortex``   2D periodic shear wave + Taylor-Green vortex (adjoint).
 ``blast``          3D spherical blast with an outward velocity shell.
+``blast_disk``     its 2D analogue for the D2Q9 model.
 ``qgp_tube_2d``    the 4 x 800 D2Q9 shock tube of Sec. V.B, Cases A-D.
 ``qgp_tube_3d``    the 1 x 1 x 800 D3Q19 shock tube of Sec. III.B at given eta/s.
 """
@@ -287,6 +288,35 @@ def blast(L: int = 512, radius: float | None = None, shell: float | None = None,
     tf = tau_v if tau_f is None else tau_f
     prm = Params(L, L, L, (ZERO_GRADIENT,) * 3, tf, tau_v, tau_e, tau_eps)
     return Problem(prm, n, 3.0 * P, u, name=f"blast_{L}x{L}x{L}")
+
+
+def blast_disk(L: int = 136, radius: float | None = None, seed: int = 1214, P_in: float = 10.0,
+               P_out: float = 0.1, umax: float = 0.6, tau_v: float = 0.9, tau_e: float = 0.62,
+               tau_eps: float = 0.8, tau_f: float | None = None, correction: int = 0) -> Problem:
+    """The 2D analogue of ``blast`` for the D2Q9 model on an L x L lattice
+    with zero-gradient faces: P = P_in inside a disk of radius L/8, P_out
+    outside (tanh width 1), n = P^(3/4), an outward velocity ring of width R/8
+    rescaled to max|u| = umax. At umax = 0.6 the ring's leading edge turns
+    cells inadmissible within a few steps."""
+    R = L / 8.0 if radius is None else radius
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = (1, L, L)
+    c = (L - 1) / 2.0
+    ax = np.arange(L, dtype=np.float64) - c
+    r = np.sqrt(ax[:, None] ** 2 + ax[None, :] ** 2)[None]
+    P = P_out + (P_in - P_out) * 0.5 * (1.0 - np.tanh(r - R))
+    n = P ** 0.75
+    mag = np.exp(-((r - R) / (R / 8.0)) ** 2) * (1.0 + 0.1 * _noise(rng, shape, ndim=2))
+    rs = np.where(r > 0, r, 1.0)
+    u = np.zeros((3,) + shape)
+    u[0] = mag * ax[None, None, :] / rs
+    u[1] = mag * ax[None, :, None] / rs
+    u *= umax / np.sqrt((u * u).sum(axis=0)).max()
+    tf = tau_v if tau_f is None else tau_f
+    prm = Params(L, L, 1, (ZERO_GRADIENT, ZERO_GRADIENT, PERIODIC), tf, tau_v, tau_e, tau_eps)
+    prm.lattice = "d2q9"
+    prm.correction = correction
+    return Problem(prm, n, 3.0 * P, u, name=f"blast_disk_{L}x{L}")
 
 
 # Initial states of the quark-gluon-plasma shock tubes in lattice units
