@@ -21,7 +21,8 @@
 // S of Eq. (31): e <- 1/tau_e, eps <- 1/tau_eps, q <- 1/tau_q, p <- 1/tau_v.
 // M has small integer entries, so m = M g and g* = g - M^T diag(1/|row|^2)
 // S (m - m_eq) are written out on sums and differences of opposite pairs.
-// The recovery is the D3Q19 one (Eq. 10 with P = eps/3) with M_z = 0.
+// The recovery is the D3Q19 one (Eq. 10 with P = eps/3) with M_z = 0, its two
+// FP64 divisions taken as refined reciprocals (recover_xy).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -235,13 +236,49 @@ __device__ __forceinline__ C7Fields c7_fields(const Macro& m, bool ok) {
   return F;
 }
 
+// FP64 reciprocal: the hardware estimate refined by two Newton-Raphson steps
+// (each squares the relative error), within an ulp or two of the IEEE
+// quotient at a fraction of the instructions of a full division.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+
+// Eq. (10) with P = eps/3 in the plane: the subluminal root
+// u = 3 M / (2E + sqrt(4E^2 - 3|M|^2)), sigma = 4E / (3 + u^2),
+// P = sigma (1 - u^2) / 4; admissible iff E > 0 and |M| < E.
+__device__ __forceinline__ bool recover_xy(double E, double Mx, double My, Macro& m) {
+  const double M2 = Mx * Mx + My * My;
+  const bool ok = (E > 0.0) && (M2 < E * E);
+  const double Es = ok ? E : 1.0;
+  const double M2s = ok ? M2 : 0.0;
+  const double q = 3.0 * rcp_nr(2.0 * Es + sqrt(4.0 * Es * Es - 3.0 * M2s));
+  m.ux = ok ? q * Mx : 0.0;
+  m.uy = ok ? q * My : 0.0;
+  m.uz = 0.0;
+  m.u2 = m.ux * m.ux + m.uy * m.uy;
+  m.sigma = 4.0 * Es * rcp_nr(3.0 + m.u2);
+  m.P = 0.25 * m.sigma * (1.0 - m.u2);
+  return ok;
+}
+
+// The recovery of the extended model in the plane: the general equation of
+// state where one is set, else recover_xy (so that the per-cell rates and the
+// fixed-rate kernels recover a cell alike, bit for bit).
+__device__ __forceinline__ bool recover_model_xy(double N, double E, double Mx, double My,
+                                                 const Ext& x, Macro& m) {
+  if (x.general_eos) return recover_general(N, E, Mx, My, 0.0, x, m);
+  return recover_xy(E, Mx, My, m);
+}
+
 // Fields of a cell from its pre-collision g (deviations from the reference).
 __device__ __forceinline__ C7Fields c7_fields_of(const double (&gd)[9], const Ref& ref) {
   const double D1 = gd[1] - gd[3], D2 = gd[2] - gd[4], D5 = gd[5] - gd[7], D6 = gd[6] - gd[8];
   const double gs =
       gd[0] + ((gd[1] + gd[3]) + (gd[2] + gd[4])) + ((gd[5] + gd[7]) + (gd[6] + gd[8]));
   Macro m;
-  const bool ok = recover(3.0 * ref.P + gs, D1 + (D5 - D6), D2 + (D5 + D6), 0.0, m);
+  const bool ok = recover_xy(3.0 * ref.P + gs, D1 + (D5 - D6), D2 + (D5 + D6), m);
   return c7_fields(m, ok);
 }
 
@@ -291,9 +328,9 @@ __device__ __forceinline__ Recovered recovered(const C (&f)[9], const C (&g)[9],
   Recovered r;
   d2q9::cell_sums(f, g, ref, r.N, r.E, r.Mx, r.My, r.fs, r.gs);
   if constexpr (EXT)
-    r.ok = recover_model(r.N, r.E, r.Mx, r.My, 0.0, *ext, r.mac);
+    r.ok = recover_model_xy(r.N, r.E, r.Mx, r.My, *ext, r.mac);
   else
-    r.ok = recover(r.E, r.Mx, r.My, 0.0, r.mac);
+    r.ok = recover_xy(r.E, r.Mx, r.My, r.mac);
   return r;
 }
 

@@ -646,7 +646,7 @@ __global__ __launch_bounds__(256) void k_d2q9_export(const T* state, int64_t cs,
     acc[3] += My;
     Macro m;
     const bool gen = d.ext.general_eos != 0;
-    const bool ok = recover_model(N, E, Mx, My, 0.0, d.ext, m);
+    const bool ok = d2q9::recover_model_xy(N, E, Mx, My, d.ext, m);
     const double nan = __builtin_nan("");
     const double e =
         !ok ? nan : (gen ? m.sigma * (1.0 - m.u2) - m.P : 0.75 * m.sigma * (1.0 - m.u2));
