@@ -105,3 +105,15 @@ def test_d2q9_traffic_names_both_corrected_kernels(tmp_path):
     assert sorted(out) == ["k_d2q9_lattice<float,128,2,1>+c7", "k_d2q9_lattice<float,64,8,1>+c7"]
     assert abs(out["k_d2q9_lattice<float,128,2,1>+c7"]["ratio"] - 1.0) < 1e-12
     assert abs(out["k_d2q9_lattice<float,64,8,1>+c7"]["ratio"] - 1.25) < 1e-12
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(here, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and "--gpus 2" in r.stderr
+    assert r.stdout == ""
