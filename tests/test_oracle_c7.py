@@ -14,6 +14,12 @@ C_7 built from y-derivatives (the flow axis) of the recovered fields. Pins:
 * Homogeneity: every term is of degree one in (sigma, P), so scaling eps and
   n by 4 scales the corrected populations by 4 exactly.
 * Mirror symmetry about the tube centre (y -> -y, u_y -> -u_y) is kept.
+* Every term at every order in u, the gamma term and theta included: sympy
+  carries the row-7 residual along the route Sec. V.B names (the change of
+  Eq. 28, gamma du -> d(gamma u), the velocity terms of d_t1(sigma u^2)),
+  which gives the printed Eq. (38) exactly; the correction the oracle applies
+  on smooth tubes at |u| up to 0.55 equals that expansion up to the O(k^2)
+  gap of central differences.
 """
 
 import numpy as np
@@ -173,3 +179,137 @@ def test_dependence_cone_is_two_cells_a_step(orc):
             st = orc.run(sub, K)
             d = max(d, np.abs(st.g[(slice(None),) + loc] - full.g[(slice(None),) + c]).max())
         assert (d == 0.0) == exact, (radius, d)
+
+
+def _c7_from_the_expansion():
+    """C_7 of this basis' row 7 (e_x^2 - e_y^2, flow along y) derived along the
+    route Sec. V.B describes, as a function of (sigma, u, d sigma/dy, du/dy).
+
+    The first-order Chapman-Enskog residual of row 7 is
+    D_7 = d_t1 m7_eq + d_y F_7, with m7_eq, F_7 and the Euler equations of
+    the model (d_t1 (sigma - P) = -d_y (sigma u), d_t1 (sigma u) =
+    -d_y (sigma u^2 + P)) all taken from the moments of the D2Q9 equilibria
+    (Eqs. 32-33). The correction replaces D_7 by the residual that gives the
+    shear stress eta d(gamma u) of Eq. (36) with no other term: the
+    isotropic-equilibrium residual -2 c_s^2 sigma gamma^-1 d(gamma u), i.e.
+    the shear term of Eq. (36) with gamma du changed to d(gamma u). Two
+    readings complete the paper's account of the velocity terms from
+    d_t1 (sigma u_z^2): the time derivative of sigma u^2 is taken as
+    2 sigma u d_t1 u, with sigma d_t1 u = d_t1 (sigma u) - u d_t1 sigma; and
+    d_t1 sigma = theta d_t1 (sigma - P) with P / sigma held fixed, so that
+    theta = sigma / (sigma - P), which equals the printed
+    1 + [(eps/P + 1) gamma^2 - 1]^-1. Returns (C, parts) with C = D_7 minus
+    the target residual, and the symbolic pieces used by the checks."""
+    sp = pytest.importorskip("sympy")
+    y = sp.symbols("y")
+    s = sp.Function("sigma")(y)
+    u = sp.Function("u")(y)
+    P = s * (1 - u ** 2) / 4  # P = eps/3 with sigma = (eps + P) gamma^2
+    gam = 1 / sp.sqrt(1 - u ** 2)
+    c2 = sp.Rational(1, 3)
+    E = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    W = [sp.Rational(4, 9)] + [sp.Rational(1, 9)] * 4 + [sp.Rational(1, 36)] * 4
+
+    def geq(a):
+        eu = E[a][1] * u
+        if a == 0:
+            return W[0] * s * (sp.Rational(9, 4) - P * (5 + 9 * c2) / (4 * s * c2)
+                               - u ** 2 / (2 * c2))
+        return W[a] * s * (P / (s * c2) + eu / c2 + eu ** 2 / (2 * c2 ** 2) - u ** 2 / (2 * c2))
+
+    g = [geq(a) for a in range(9)]
+    r7 = [ex * ex - ey * ey for ex, ey in E]
+    m7 = sum(r * q for r, q in zip(r7, g))
+    F7 = sum(r * E[a][1] * g[a] for a, r in enumerate(r7))
+    En = sum(g)
+    Mo = sum(E[a][1] * g[a] for a in range(9))
+    Pyy = sum(E[a][1] ** 2 * g[a] for a in range(9))
+    dt_E = -sp.diff(Mo, y)
+    dt_M = -sp.diff(Pyy, y)
+    theta = s / En
+    dt_s = theta * dt_E
+    s_dt_u = dt_M - u * dt_s
+    dt_m7 = -2 * u * s_dt_u  # m7_eq = -sigma u^2 (checked by the next test)
+    D7 = dt_m7 + sp.diff(F7, y)
+    target = -2 * c2 * s / gam * sp.diff(gam * u, y)
+    C = D7 - target
+    S, U, dS, dU = sp.symbols("S U dS dU")
+    flat = C.subs({sp.Derivative(s, y): dS, sp.Derivative(u, y): dU}).subs({s: S, u: U})
+    parts = {"sp": sp, "y": y, "s": s, "u": u, "P": P, "gam": gam, "c2": c2, "m7": m7,
+             "F7": F7, "E": En, "M": Mo, "Pyy": Pyy, "theta": theta, "C": C,
+             "args": (S, U, dS, dU)}
+    return sp.lambdify((S, U, dS, dU), sp.simplify(flat), "numpy"), parts
+
+
+def test_expansion_route_reproduces_eq38():
+    """The moments the derivation uses are those of Eqs. (32)-(33), theta is
+    the printed one, and the route gives the printed C_7 to all orders in u
+    (with the sign of this basis' row 7)."""
+    _, d = _c7_from_the_expansion()
+    sp, y, s, u, P, gam, c2 = (d[k] for k in ("sp", "y", "s", "u", "P", "gam", "c2"))
+    assert sp.simplify(d["m7"] + s * u ** 2) == 0
+    assert sp.simplify(d["F7"] + (1 - c2) * s * u) == 0
+    assert sp.simplify(d["E"] - (s - P)) == 0
+    assert sp.simplify(d["M"] - s * u) == 0
+    assert sp.simplify(d["Pyy"] - (s * u ** 2 + P)) == 0
+    eps = 3 * P
+    theta_printed = 1 + 1 / ((eps / P + 1) * gam ** 2 - 1)
+    assert sp.simplify(d["theta"] - theta_printed) == 0
+    dd = lambda q: sp.diff(q, y)  # noqa: E731
+    printed = 2 * (u * dd(c2 * s - P) - c2 * s / gam * u * dd(gam) - u * dd(s * u ** 2)
+                   + u ** 2 * theta_printed * dd(s * u))
+    assert sp.simplify(sp.expand(d["C"] + printed)) == 0
+
+
+def _tube_fields(orc, L, umax, tau_v):
+    """One-step runs of a smooth periodic 1 x L flow along y with and without
+    the correction: the fields the corrected step differentiates, and the
+    change of m_7 the correction made, divided by (1 - s_v / 2)."""
+    k = 2 * np.pi / L
+    y = np.arange(L)
+    runs = {}
+    for corr in (0, 1):
+        prob = _tube(L, correction=corr, tau_v=tau_v)
+        prob.eps[0, :, 0] = 1.0 + 0.3 * np.cos(k * y + 0.3)
+        prob.n[0, :, 0] = 1.0 + 0.2 * np.sin(k * y)
+        prob.u[1, 0, :, 0] = umax * (0.8 * np.sin(k * y) + 0.2 * np.sin(2 * k * y + 1.0))
+        runs[corr] = orc.run(prob, 1)
+    # collision conserves N, E, M: the fields of the uncorrected state after
+    # one step are those of the pulled populations both runs collided
+    F = runs[0].fields()
+    M = orc.d2q9_tables()["M"]
+    dm7 = (M @ (runs[1].g - runs[0].g).reshape(9, L))[7] / (1.0 - 0.5 / tau_v)
+    eps, P, gam = F["eps"][0, :, 0], F["P"][0, :, 0], F["gamma"][0, :, 0]
+    uy = F["u"][1, 0, :, 0]
+    sig = (eps + P) * gam * gam
+    cd = lambda a: 0.5 * (np.roll(a, -1) - np.roll(a, 1))  # noqa: E731
+    return dm7, sig, uy, cd(sig), cd(uy)
+
+
+@pytest.mark.parametrize("umax", [0.3, 0.55])
+def test_correction_equals_the_expansion_at_every_order(orc, umax):
+    """Pins every term of Eq. (38), the gamma term and theta included: the
+    correction the oracle applies at each cell of a smooth tube equals the
+    expansion of _c7_from_the_expansion, evaluated with central differences
+    of sigma and u. What remains is the gap between a central difference of
+    a product and the product rule, O(k^2): it falls fourfold from
+    k = 2 pi / 1024 to 2 pi / 2048, and is below 1e-4 of the term there.
+    Dropping the gamma term, or taking theta = 1 or its rest value 4/3,
+    would move the result by more than 50 times that tolerance."""
+    C, d = _c7_from_the_expansion()
+    gaps = []
+    for L in (1024, 2048):
+        dm7, sig, uy, ds, du = _tube_fields(orc, L, umax, 1.7)
+        want = C(sig, uy, ds, du)
+        gaps.append(np.abs(dm7 - want).max() / np.abs(want).max())
+    assert gaps[1] < 1e-4, gaps
+    assert 3.5 < gaps[0] / gaps[1] < 4.5, gaps
+    # each higher-order piece is far above the tolerance on this flow
+    tol = 1e-4 * np.abs(want).max()
+    gam2 = 1.0 / (1.0 - uy * uy)
+    gamma_term = 2.0 / 3.0 * sig * gam2 * uy * uy * du  # 2 c_s^2 sigma gamma^-1 u dgamma
+    theta = 4.0 * gam2 / (4.0 * gam2 - 1.0)
+    theta_term = 2.0 * uy * uy * (uy * ds + sig * du)  # per unit of theta
+    assert np.abs(gamma_term).max() > 50 * tol
+    assert np.abs((theta - 1.0) * theta_term).max() > 50 * tol
+    assert np.abs((theta - 4.0 / 3.0) * theta_term).max() > 50 * tol
