@@ -3,12 +3,20 @@
 Every source is compiled with hipcc for gfx950 only, with packed FP32 ops
 disabled, into position-independent objects linked into one shared library
 that sits next to this file.
+
+The build refuses any kernel that uses scratch (private) memory, i.e. that
+spills registers: the compiler's kernel resource report is read for every
+kernel of every source, and a ScratchSize above zero fails the build with the
+kernels named. Spilled builds are the class that once returned wrong results
+from a graph-launched persistent kernel (FP64, 1024 threads, general equation
+of state), and no kernel here needs scratch otherwise.
 """
 
 from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import subprocess
 import sys
 
@@ -25,14 +33,35 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-ffp-c
          "-I" + os.path.join(HERE, "..", "include")]
 
 
+def scratch_users(report: str) -> dict:
+    """Kernels with a nonzero ScratchSize in hipcc's
+    -Rpass-analysis=kernel-resource-usage output: {mangled name: bytes per lane}."""
+    out, name = {}, None
+    for line in report.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and name and int(m.group(1)) > 0:
+            out[name] = int(m.group(1))
+    return out
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj,
+           "-Rpass-analysis=kernel-resource-usage"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+    users = scratch_users(r.stderr)
+    if users:
+        names = "\n".join(f"  {k}: {v} B/lane" for k, v in sorted(users.items()))
+        raise RuntimeError(f"{src}: kernels that use scratch memory (register spills) are "
+                           f"refused:\n{names}")
     return obj
 
 

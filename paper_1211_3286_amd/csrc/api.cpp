@@ -637,10 +637,6 @@ rlb_status launch_persistent(rlb_sim* h, int variant, int nsteps, int pingpong, 
       RLB_HIP(rlb::d2q9_member_kernel(h->precision, variant, h->corr, h->ext, &func, &block));
     else
       RLB_HIP(rlb::member_kernel(h->precision, variant, h->ext, &func, &block));
-    // Extended-model kernels run with at most 512 threads per block: the
-    // 1024-thread builds spill registers to scratch, and one of them
-    // (FP64, one cell per thread) returned wrong results on gfx950.
-    if (h->ext && block.x > 512) return RLB_E_UNSUPPORTED;
     args[0] = &h->margs;
     grid = dim3(h->n_members, 1, 1);
   }
@@ -868,7 +864,9 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
   h->corr = opt->correction != 0;
   h->q = nvel(opt->lattice);
   h->lattice = lattice_path(n_members, L.ncells);
-  h->variant = h->d2 ? 2 : (h->lattice ? 3 : 2);
+  // defaults: the lattice path's 256 x 1 block; the persistent path's 512
+  // threads with one cell each
+  h->variant = h->d2 ? (h->lattice ? 2 : 1) : (h->lattice ? 3 : 1);
   h->all_tubes = !h->d2;
   for (int i = 0; i < n_members; ++i)
     if (members[i].nx != 1 || members[i].ny != 1) h->all_tubes = false;
@@ -912,7 +910,6 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
     if (p.eta_over_s > 0.0 || d.ext.general_eos) h->ext = true;
     off += d.ncells;
   }
-  if (h->ext && !h->lattice) h->variant = 1;  // 512 threads (see launch_persistent)
   const double *dn, *de, *du;
   if (hipMemsetAsync(h->d_small, 0, 1024, h->stream) != hipSuccess ||
       hipMemsetAsync(h->d_bad, 0, rlb::kBadBytes, h->stream) != hipSuccess)

@@ -541,7 +541,9 @@ __global__ __launch_bounds__(256) void k_reduce(const double* partials, int npar
 constexpr LatticeVariant kLat[] = {{64, 1, 1}, {64, 4, 1}, {128, 2, 1}, {256, 1, 1},
                                    {64, 4, 2}, {256, 1, 2}, {128, 2, 4}, {256, 1, 4}};
 constexpr int kNumLat = sizeof(kLat) / sizeof(kLat[0]);
-constexpr MemberVariant kMem[] = {{256, 1}, {512, 1}, {1024, 1}, {256, 2}, {512, 2}, {1024, 2}};
+// At most 512 threads: with 1024 (4 waves per SIMD, at most 128 VGPRs) every
+// member build spills to scratch, which the build refuses for every kernel.
+constexpr MemberVariant kMem[] = {{256, 1}, {512, 1}, {256, 2}, {512, 2}};
 constexpr int kNumMem = sizeof(kMem) / sizeof(kMem[0]);
 
 constexpr MemberVariant kSeg[] = {{256, 1}, {256, 2}, {512, 1}, {128, 4}, {256, 4}};
@@ -626,10 +628,8 @@ const void* mem_func(int v) {
   switch (v) {
     case 0: return (const void*)&k_step_members<T, 256, 1, EXT>;
     case 1: return (const void*)&k_step_members<T, 512, 1, EXT>;
-    case 2: return (const void*)&k_step_members<T, 1024, 1, EXT>;
-    case 3: return (const void*)&k_step_members<T, 256, 2, EXT>;
-    case 4: return (const void*)&k_step_members<T, 512, 2, EXT>;
-    case 5: return (const void*)&k_step_members<T, 1024, 2, EXT>;
+    case 2: return (const void*)&k_step_members<T, 256, 2, EXT>;
+    case 3: return (const void*)&k_step_members<T, 512, 2, EXT>;
   }
   return nullptr;
 }
@@ -719,12 +719,10 @@ const char* lattice_kernel_name(int precision, int v) {
 }
 
 const char* member_kernel_name(int precision, int v) {
-  static const char* n32[] = {"k_step_members<float,256,1>",  "k_step_members<float,512,1>",
-                              "k_step_members<float,1024,1>", "k_step_members<float,256,2>",
-                              "k_step_members<float,512,2>",  "k_step_members<float,1024,2>"};
-  static const char* n64[] = {"k_step_members<double,256,1>",  "k_step_members<double,512,1>",
-                              "k_step_members<double,1024,1>", "k_step_members<double,256,2>",
-                              "k_step_members<double,512,2>",  "k_step_members<double,1024,2>"};
+  static const char* n32[] = {"k_step_members<float,256,1>", "k_step_members<float,512,1>",
+                              "k_step_members<float,256,2>", "k_step_members<float,512,2>"};
+  static const char* n64[] = {"k_step_members<double,256,1>", "k_step_members<double,512,1>",
+                              "k_step_members<double,256,2>", "k_step_members<double,512,2>"};
   if (v < 0 || v >= kNumMem) return "?";
   return precision ? n32[v] : n64[v];
 }

@@ -688,7 +688,8 @@ constexpr LatticeVariant kLat2[] = {{64, 1, 1},  {128, 1, 1}, {256, 1, 1}, {64, 
                                     {128, 2, 1}, {256, 1, 2}, {256, 1, 4}, {128, 2, 4},
                                     {64, 8, 1},  {128, 4, 1}};
 constexpr int kNumLat2 = sizeof(kLat2) / sizeof(kLat2[0]);
-constexpr MemberVariant kMem2[] = {{256, 1}, {512, 1}, {1024, 1}, {512, 2}, {1024, 2}};
+// At most 512 threads: the 1024-thread builds spill to scratch (refused by the build).
+constexpr MemberVariant kMem2[] = {{256, 1}, {512, 1}, {512, 2}};
 constexpr int kNumMem2 = sizeof(kMem2) / sizeof(kMem2[0]);
 // strip rounds: threads per block, steps per launch
 constexpr TubeVariant kStrip2[] = {{128, 2}, {128, 4}, {256, 4}, {256, 8}, {512, 8}, {512, 16}};
@@ -764,9 +765,7 @@ const void* mem2_func(int v) {
   switch (v) {
     case 0: return (const void*)&k_d2q9_members<T, 256, 1, CORR, EXT>;
     case 1: return (const void*)&k_d2q9_members<T, 512, 1, CORR, EXT>;
-    case 2: return (const void*)&k_d2q9_members<T, 1024, 1, CORR, EXT>;
-    case 3: return (const void*)&k_d2q9_members<T, 512, 2, CORR, EXT>;
-    case 4: return (const void*)&k_d2q9_members<T, 1024, 2, CORR, EXT>;
+    case 2: return (const void*)&k_d2q9_members<T, 512, 2, CORR, EXT>;
   }
   return nullptr;
 }
@@ -886,11 +885,9 @@ hipError_t d2q9_member_kernel(int precision, int v, bool corr, bool ext, const v
 
 const char* d2q9_member_kernel_name(int precision, int v) {
   static const char* n32[] = {"k_d2q9_members<float,256,1>", "k_d2q9_members<float,512,1>",
-                              "k_d2q9_members<float,1024,1>", "k_d2q9_members<float,512,2>",
-                              "k_d2q9_members<float,1024,2>"};
+                              "k_d2q9_members<float,512,2>"};
   static const char* n64[] = {"k_d2q9_members<double,256,1>", "k_d2q9_members<double,512,1>",
-                              "k_d2q9_members<double,1024,1>", "k_d2q9_members<double,512,2>",
-                              "k_d2q9_members<double,1024,2>"};
+                              "k_d2q9_members<double,512,2>"};
   if (v < 0 || v >= kNumMem2) return "?";
   return precision ? n32[v] : n64[v];
 }

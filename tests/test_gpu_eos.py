@@ -131,21 +131,19 @@ def test_device_validation_of_the_rest_energy():
     assert ei.value.code == -3
 
 
-def test_extended_persistent_kernels_stay_at_512_threads():
-    """The extended-model persistent kernels run with at most 512 threads per
-    block (the 1024-thread builds spill to scratch and one returned wrong
-    results): those variants are refused and the default avoids them."""
+def test_persistent_kernels_stay_at_512_threads():
+    """Every persistent member kernel runs with at most 512 threads per block
+    (the 1024-thread builds spilled registers to scratch, which the build now
+    refuses for every kernel; one of them returned wrong results), and the
+    default of the persistent path is the 512-thread one-cell kernel."""
     import paper_1211_3286_amd as rlb
-    prob = _random(13, 11, 7, (1, 0, 1), "d3q19")
-    sim = rlb.from_problems(prob, precision=FP64)
-    assert "512" in sim.kernel_name
-    for v, name in enumerate(sim.variants()):
-        if name.startswith("k_step_members") and ",1024," in name:
-            s2 = rlb.from_problems(prob, precision=FP64)
-            s2.variant = v
-            with pytest.raises(rlb.RLBError) as ei:
-                s2.step(1)
-            assert ei.value.code == -7
+    for lattice, dims in (("d3q19", (13, 11, 7)), ("d2q9", (13, 11, 1))):
+        prob = _random(*dims, (1, 0, 1) if lattice == "d3q19" else (1, 0, 0), lattice)
+        sim = rlb.from_problems(prob, precision=FP64)
+        assert sim.kernel_name.startswith(("k_step_members", "k_d2q9_members"))
+        assert ",512,1>" in sim.kernel_name
+        assert not any(",1024," in n for n in sim.variants() if "members" in n)
+        sim.close()
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
