@@ -77,8 +77,10 @@ typedef enum {
   RLB_E_WORKSPACE = -4,   /* workspace NULL, misaligned (needs 256 B) or too small */
   RLB_E_DEVICE = -5,      /* a HIP runtime call failed */
   RLB_E_STATE = -6,       /* call not valid in this state (e.g. rlb_grad without tape) */
-  RLB_E_UNSUPPORTED = -7  /* valid request the library does not provide (e.g.
+  RLB_E_UNSUPPORTED = -7, /* valid request the library does not provide (e.g.
                              tube rounds for a batch that is not all 1 x 1 x L) */
+  RLB_E_SCRATCH = -8      /* rlb_run_noalloc: the lattice does not fit the fixed
+                             scratch array of RLB_NOALLOC_SCRATCH_BYTES */
 } rlb_status;
 
 enum { RLB_PERIODIC = 0, RLB_ZERO_GRADIENT = 1 };
@@ -245,6 +247,46 @@ rlb_status rlb_info(rlb_handle h, int64_t* steps, char* kernel_name, size_t bufl
 void rlb_free(rlb_handle h);
 
 const char* rlb_status_string(rlb_status s);
+
+/* ---------------------------------------------------------------------------
+ * Allocation-free run, for callers that cannot allocate memory: tight serving
+ * or sweep loops, harnesses that forbid allocation, callers that hold no
+ * workspace. It does what rlb_init + rlb_step(nsteps) + rlb_moments do on
+ * one lattice (single member, fixed options), with the same kernels, and
+ * allocates nothing: no device or host memory, no handle, no HIP graph.
+ *
+ * Everything besides the caller's fields (the two population buffers, the
+ * member descriptor, the partial sums and the inadmissible-cell counters)
+ * lives in one fixed device array of RLB_NOALLOC_SCRATCH_BYTES inside the
+ * library. Each device the call runs on holds its own copy of that array
+ * until the process ends. A lattice whose state does not fit it returns
+ * RLB_E_SCRATCH before any device work: about 2 x 2 x 19 x sizeof(precision)
+ * bytes per cell on D3Q19 (2 x 2 x 9 x ... on D2Q9), e.g. up to about 220,000
+ * cells in FP32 and 110,000 in FP64 on D3Q19.
+ *
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; each call clears its counters first. Calls on one device are
+ * serialised by a lock inside the library (each call waits for its own stream
+ * before it returns), so threads of one process may call it concurrently;
+ * device work of another process has its own copy.
+ *
+ *   member, opt: host. opt->ckpt_every must be 0 (else RLB_E_UNSUPPORTED);
+ *     opt->diag_every and opt->tape_steps are ignored; every other option and
+ *     parameter as for rlb_init (same checks, same status codes).
+ *   n0, eps0, u0: device, the initial fields (layout of rlb_init), read only.
+ *   nsteps >= 0: steps to advance.
+ *   n, eps, P, gamma, u: device outputs of the fields after nsteps, as
+ *     rlb_moments with out_on_device = 1; any may be NULL.
+ *   sums: host, 5 doubles or NULL; n_unphysical: host or NULL (as rlb_moments).
+ *   hip_stream: hipStream_t (NULL = null stream); the call synchronises it.
+ * Returns RLB_E_UNPHYSICAL for inadmissible input cells (nothing computed) or
+ * cells that became inadmissible (outputs written, as rlb_moments). */
+#define RLB_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+rlb_status rlb_run_noalloc(const rlb_params* member, const rlb_options* opt,
+                           const double* n0, const double* eps0, const double* u0,
+                           int32_t nsteps, double* n, double* eps, double* P, double* gamma,
+                           double* u, double sums[5], int64_t* n_unphysical,
+                           void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,9 @@ LIB_PATH = os.path.join(_HERE, "librlb.so")
 
 RLB_OK = 0
 STATUS = {0: "RLB_OK", -1: "RLB_E_ARG", -2: "RLB_E_TAU", -3: "RLB_E_UNPHYSICAL",
-          -4: "RLB_E_WORKSPACE", -5: "RLB_E_DEVICE", -6: "RLB_E_STATE", -7: "RLB_E_UNSUPPORTED"}
+          -4: "RLB_E_WORKSPACE", -5: "RLB_E_DEVICE", -6: "RLB_E_STATE", -7: "RLB_E_UNSUPPORTED",
+          -8: "RLB_E_SCRATCH"}
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024  # RLB_NOALLOC_SCRATCH_BYTES
 FP64, FP32 = 0, 1
 PERIODIC, ZERO_GRADIENT = 0, 1
 D3Q19, D2Q9 = 0, 1
@@ -37,7 +39,7 @@ LATTICE_NAMES = {"d3q19": D3Q19, "d2q9": D2Q9}
 ENTRY_POINTS = ["rlb_workspace_size", "rlb_init", "rlb_step", "rlb_moments", "rlb_diagnostics",
                 "rlb_populations", "rlb_grad", "rlb_num_variants", "rlb_variant_name",
                 "rlb_set_variant", "rlb_get_variant", "rlb_tune", "rlb_info", "rlb_free",
-                "rlb_status_string"]
+                "rlb_status_string", "rlb_run_noalloc"]
 
 
 class RLBError(RuntimeError):
@@ -100,6 +102,8 @@ def lib() -> ctypes.CDLL:
     L.rlb_info.argtypes = [vp, ctypes.POINTER(i64), ctypes.c_char_p, sz]
     L.rlb_free.argtypes = [vp]
     L.rlb_free.restype = None
+    L.rlb_run_noalloc.argtypes = [P, O, vp, vp, vp, i32, vp, vp, vp, vp, vp, dp,
+                                  ctypes.POINTER(i64), vp]
     L.rlb_status_string.argtypes = [i32]
     L.rlb_status_string.restype = ctypes.c_char_p
     for name in ENTRY_POINTS:
@@ -357,6 +361,36 @@ class Simulation:
         shape = shapes[0] if len(shapes) == 1 else f"{len(shapes)}x{self.ncells}"
         lat = ("d2q9|" if self.lattice == D2Q9 else "") + ("c7|" if self.opt.correction else "")
         return f"{dev}|{lat}{'fp32' if self.precision == FP32 else 'fp64'}|{shape}"
+
+
+def run_noalloc(params, n0, eps0, u0, nsteps: int, precision: int = FP32, lattice=D3Q19,
+                correction: int = 0, stream=None, allow_unphysical: bool = False) -> Dict:
+    """rlb_run_noalloc: rlb_init + rlb_step(nsteps) + rlb_moments on one
+    lattice with no allocation in the library (its fixed scratch array holds
+    the state). Fields are float64 device tensors; returns the rlb_moments
+    outputs as Simulation.moments does."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1211_3286_amd needs a ROCm GPU; none is visible")
+    dev = torch.device("cuda", torch.cuda.current_device())
+    nc = int(params.nx) * int(params.ny) * int(params.nz)
+    fields = [t.to(device=dev, dtype=torch.float64).contiguous() for t in (n0, eps0, u0)]
+    out = {k: torch.empty(nc, dtype=torch.float64, device=dev) for k in ("n", "eps", "P", "gamma")}
+    out["u"] = torch.empty(3, nc, dtype=torch.float64, device=dev)
+    opt = options(precision, 0, 0, 0, lattice, correction)
+    arr = cparams([params])
+    sums = (ctypes.c_double * 5)()
+    bad = ctypes.c_int64(0)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    code = lib().rlb_run_noalloc(arr, ctypes.byref(opt), *[_dptr(t) for t in fields], int(nsteps),
+                                 _dptr(out["n"]), _dptr(out["eps"]), _dptr(out["P"]),
+                                 _dptr(out["gamma"]), _dptr(out["u"]), sums, ctypes.byref(bad),
+                                 int(st.cuda_stream))
+    if code != RLB_OK and not (allow_unphysical and code == -3 and bad.value > 0):
+        _check(code, "rlb_run_noalloc")
+    out["sums"] = np.array(sums[:])
+    out["bad"] = int(bad.value)
+    return out
 
 
 def problem_fields(problems) -> tuple:

@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librlb.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "kernels2d.hip", "adjoint.hip", "noalloc.hip", "api.cpp"]
 HEADERS = ["cell.hpp", "cell2d.hpp", "adjoint_cell.hpp", "device_util.hpp", "internal.hpp",
            "adjoint.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

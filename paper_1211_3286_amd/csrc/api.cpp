@@ -802,6 +802,7 @@ const char* rlb_status_string(rlb_status s) {
     case RLB_E_DEVICE: return "HIP runtime error";
     case RLB_E_STATE: return "call not valid in the current state";
     case RLB_E_UNSUPPORTED: return "unsupported configuration";
+    case RLB_E_SCRATCH: return "lattice too large for the fixed scratch array of rlb_run_noalloc";
   }
   return "unknown status";
 }

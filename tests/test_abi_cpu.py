@@ -32,7 +32,7 @@ def test_header_entry_points_exported():
 
 
 def test_status_strings():
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         s = rlb.status_string(code)
         assert s and s != "unknown status"
     assert rlb.status_string(-99) == "unknown status"
@@ -204,3 +204,31 @@ def test_equation_of_state_parameters_validated():
     opt = rlb.options()
     _, need = _size([p], opt)
     assert _init([p], _fields(96, eps=1.0, n=1.0), 1 << 40, need, opt) == -3
+
+
+def _noalloc(member, opt, nsteps=1, fields=True):
+    """rlb_run_noalloc with placeholder field pointers: every case here is
+    rejected before the library touches them or the device."""
+    arr = rlb.cparams([member])
+    dummy = ctypes.c_void_p(0x1000) if fields else None
+    bad = ctypes.c_int64(-1)
+    return rlb.lib().rlb_run_noalloc(arr, ctypes.byref(opt), dummy, dummy, dummy, nsteps, None,
+                                     None, None, None, None, None, ctypes.byref(bad), None)
+
+
+def test_noalloc_rejects_before_device_work():
+    """The allocation-free run checks what rlb_init checks, and refuses a
+    lattice whose state does not fit its fixed scratch array
+    (RLB_NOALLOC_SCRATCH_BYTES) with RLB_E_SCRATCH."""
+    ok = _p()
+    assert _noalloc(ok, rlb.options(rlb.FP32), fields=False) == -1
+    assert _noalloc(ok, rlb.options(rlb.FP32), nsteps=-1) == -1
+    assert _noalloc(_p(tau_v=0.5), rlb.options(rlb.FP32)) == -2
+    assert _noalloc(_p(nx=0), rlb.options(rlb.FP32)) == -1
+    assert _noalloc(ok, rlb.options(rlb.FP32, ckpt_every=5, tape_steps=10)) == -7
+    assert _noalloc(ok, rlb.options(rlb.FP32, correction=1)) == -7
+    # 64^3 FP64: 2 buffers x 38 planes x 8 B x 262,144 cells = 159 MB > 64 MiB
+    assert _noalloc(_p(nx=64, ny=64, nz=64), rlb.options(rlb.FP64)) == -8
+    # FP32: 61^3 (226,981 cells x 304 B = 69 MB) exceeds it as well
+    assert _noalloc(_p(nx=61, ny=61, nz=61), rlb.options(rlb.FP32)) == -8
+    assert rlb.status_string(-8).startswith("lattice too large")
