@@ -7,12 +7,16 @@ random flow from 16 Fourier modes (|k| <= 4, max|u| = 0.1, eps and n = 1 +
 FP32 populations with FP64 recovery and FP64 conservation sums fused into
 every step. One timed step = one fused kernel launch over all 16.8M cells.
 
-Also reported ("forms"): the same step in FP64, the batched persistent
-launch over 64 ragged shock tubes (3000 steps, one graph launch), the
-adjoint gradient of a 512 x 512 run (1000 steps, checkpoints every 50), the
-512^3 blast, the D2Q9 MRT model of Sec. V (a 4096^2 lattice, the
-4 x 800 Cases A-D batch, the correction of Eqs. 37-38), and relaxation times
-set per cell from eta/s.
+Also reported ("forms"): the same step in FP64, the 1 x 1 x 800 FP64 shock
+tube (2000 steps), the batch of 64 ragged shock tubes (3000 steps, one HIP
+graph launch whose kernel nodes are rounds of H steps: kernel_nodes states
+how many), the adjoint gradient of a 512 x 512 run (1000 steps, checkpoints
+every 50), the 512^3 blast, the D2Q9 MRT model of Sec. V (a 4096^2 lattice,
+the 4 x 800 Cases A-D batch, the correction of Eqs. 37-38), and relaxation
+times set per cell from eta/s. Every form states its error: a short live run
+of the timed kernel variant against the FP64 oracle from the same input
+(error_vs_oracle), and for the adjoint the error of dL/dtau against central
+finite differences and of every output against the oracle's own adjoint.
 
 Prints one JSON line. ``value`` is MLUPS (million lattice-cell updates per
 second) with the populations resident in HBM; ``roofline`` prices the fused
@@ -40,21 +44,49 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM roofline, FP32 vs FP64 step, batched and adjoint, at stated error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+D2Q9_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_d2q9.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_d2q9.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1211_3286_amd", "csrc", f)
                   for f in ("cell.hpp", "device_util.hpp", "internal.hpp", "kernels.hip",
                             "api.cpp")]
+D2Q9_SOURCES = [os.path.join(ROOT, "paper_1211_3286_amd", "csrc", f)
+                for f in ("cell.hpp", "cell2d.hpp", "device_util.hpp", "internal.hpp",
+                          "kernels2d.hip", "api.cpp")]
+# MI355X: 256 CUs at 2.4 GHz, each issuing at most one wave64 VALU
+# instruction a cycle (4 SIMDs, 4 cycles per wave64 instruction)
+VALU_PEAK_GINST = 256 * 2.4
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
+    for p in sources or KERNEL_SOURCES:
         with open(p, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def _record(path: str, kernel: str):
+    """A kernel's entry of a committed D2Q9 counter record, if the record
+    still describes the current D2Q9 sources (else None)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        db = json.load(fh)
+    if db.get("source_hash") != kernel_hash(D2Q9_SOURCES):
+        return None
+    return db.get("kernels", {}).get(kernel)
+
+
+def measured_d2q9(kernel: str):
+    return _record(D2Q9_TRAFFIC_FILE, kernel)
+
+
+def measured_valu(kernel: str):
+    return _record(VALU_FILE, kernel)
 
 
 def measured_traffic(kernel: str, cells: int):
@@ -129,7 +161,61 @@ def bench_lattice(torch, rlb, wl, n: int, precision: int, steps: int, warmup: in
     return out
 
 
-def bench_batched(torch, rlb, wl, steps: int = 3000):
+def graph_shape(kernel: str, steps: int) -> dict:
+    """What one rlb_step of a persistent-path variant launches: the tube and
+    strip rounds are a HIP graph of ceil(steps / H) kernel nodes (H steps
+    each, from the variant name's /hH); the one-block and segmented kernels
+    are one node doing every step."""
+    m = re.search(r"/h(\d+)", kernel)
+    h = int(m.group(1)) if m else None
+    return {"graph_launches": 1, "kernel_nodes": -(-steps // h) if h else 1,
+            "steps_per_node": h if h else steps}
+
+
+def live_error(torch, rlb, problems, steps: int, precision: int, kernel, **kw):
+    """Max-norm errors of a short GPU run (the kernel variant that was timed)
+    against the FP64 oracle from the same input: populations, n, eps over
+    every cell (max|a - b| / max|b| per array) and u (max|a - b|), each the
+    worst over the members; plus the inadmissible count of each side."""
+    import numpy as np
+    import oracle
+    if not isinstance(problems, (list, tuple)):
+        problems = [problems]
+    sim = rlb.from_problems(problems, precision=precision, **kw)
+    sim.variant = kernel if isinstance(kernel, int) else sim.variants().index(kernel)
+    sim.step(steps)
+    f, g = sim.populations()
+    m = sim.moments(allow_unphysical=True)
+    f, g = f.cpu().numpy(), g.cpu().numpy()
+    gpu = {k: m[k].cpu().numpy() for k in ("n", "eps", "u")}
+    sim.close()
+    err = {"steps": steps, "cells": int(sum(p.params.ncells for p in problems))}
+    worst = dict.fromkeys(("f", "g", "n", "eps", "u"), 0.0)
+    bad_o = 0
+    off = 0
+    for p in problems:
+        st = oracle.run(p, steps)
+        F = st.fields()
+        bad_o += st.bad
+        nc = p.params.ncells
+        sl = slice(off, off + nc)
+        pairs = {"f": (f[:, sl], st.f.reshape(f.shape[0], nc)),
+                 "g": (g[:, sl], st.g.reshape(g.shape[0], nc)),
+                 "n": (gpu["n"][sl], F["n"].ravel()), "eps": (gpu["eps"][sl], F["eps"].ravel()),
+                 "u": (gpu["u"][:, sl], F["u"].reshape(3, nc))}
+        for k, (a, b) in pairs.items():
+            keep = np.isfinite(a) & np.isfinite(b)
+            if not keep.any():
+                continue
+            d = np.abs(a[keep] - b[keep]).max()
+            worst[k] = max(worst[k], float(d if k == "u" else d / np.abs(b[keep]).max()))
+        off += nc
+    err.update(worst)
+    err["inadmissible_gpu"], err["inadmissible_oracle"] = m["bad"], int(bad_o)
+    return err
+
+
+def bench_batched(torch, rlb, wl, steps: int = 3000, check_steps: int = 200):
     tubes = wl.tube_batch()
     sim = rlb.from_problems(tubes, precision=rlb.FP32)
     tune = sim.tune(trial_steps=50)
@@ -148,10 +234,63 @@ def bench_batched(torch, rlb, wl, steps: int = 3000):
            "tube_steps_per_s": len(tubes) * steps / (ms * 1e-3),
            "mlups": cells * steps / (ms * 1e-3) / 1e6,
            "effective_gbs": 304 * cells * steps / (ms * 1e-3) / 1e9,
-           "kernel": sim.kernel_name, "launches": 1, "graph": True, "inadmissible": m["bad"],
+           "kernel": sim.kernel_name, **graph_shape(sim.kernel_name, steps),
+           "inadmissible": m["bad"],
            "note": "working set ~35 MB stays in L2/MALL; effective GB/s is not HBM traffic"}
     sim.close()
+    # every tube against the oracle over a short run of the timed variant (the
+    # tests hold the 3000-step per-tube errors)
+    res["error_vs_oracle"] = live_error(torch, rlb, tubes, check_steps, rlb.FP32, res["kernel"])
     return res
+
+
+def bench_shock_tube(torch, rlb, wl, steps: int = 2000, dump_every: int = 200):
+    """The 1 x 1 x 800 FP64 shock tube (zero-gradient long axis, tau = 0.9):
+    GPU steps per second over 2000 steps in one rlb_step call (the tuned
+    persistent variant), and the max-norm error against the oracle at every
+    dump of a second run stopped every 200 steps; the same in FP32."""
+    import numpy as np
+    import oracle
+    prob = wl.shock_tube(800)
+    st = oracle.State.init(prob)
+    ref = []
+    for _ in range(steps // dump_every):
+        st.step(dump_every)
+        F = st.fields()
+        ref.append({"f": st.f.reshape(19, -1).copy(), "g": st.g.reshape(19, -1).copy(),
+                    "n": F["n"].ravel(), "eps": F["eps"].ravel(), "u": F["u"].reshape(3, -1)})
+    out = {"lattice": "1x1x800", "steps": steps, "dump_every": dump_every}
+    for prec, name in ((rlb.FP64, "fp64"), (rlb.FP32, "fp32")):
+        sim = rlb.from_problems(prob, precision=prec)
+        tune = sim.tune(trial_steps=50)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        sim.close()
+        # the dumps: a fresh run stopping every dump_every steps
+        sim = rlb.from_problems(prob, precision=prec)
+        sim.variant = sim.variants().index(tune["name"])
+        worst = dict.fromkeys(("f", "g", "n", "eps", "u"), 0.0)
+        for r in ref:
+            sim.step(dump_every)
+            f, g = sim.populations()
+            m = sim.moments()
+            gpu = {"f": f.cpu().numpy(), "g": g.cpu().numpy(), "n": m["n"].cpu().numpy(),
+                   "eps": m["eps"].cpu().numpy(), "u": m["u"].cpu().numpy()}
+            for k, a in gpu.items():
+                d = np.abs(a - r[k]).max()
+                worst[k] = max(worst[k], float(d if k == "u" else d / np.abs(r[k]).max()))
+        sim.close()
+        out[name] = {"ms_total": ms, "steps_per_s": steps / (ms * 1e-3),
+                     "mlups": 800 * steps / (ms * 1e-3) / 1e6, "kernel": tune["name"],
+                     **graph_shape(tune["name"], steps),
+                     "error_vs_oracle_over_dumps": worst}
+    return out
 
 
 def bench_blast(torch, rlb, wl, L: int = 512, steps: int = 400, warmup: int = 10):
@@ -175,42 +314,127 @@ def bench_blast(torch, rlb, wl, L: int = 512, steps: int = 400, warmup: int = 10
            "inadmissible_fraction": m["bad"] / float(cells * (steps + warmup)),
            "max_u_admissible": float(torch.nan_to_num(m["u"].norm(dim=0), nan=0.0).max().item()),
            "workspace_gb": sim.ws_bytes / 1e9}
+    variant = sim.variant
     sim.close()
     del m
     torch.cuda.empty_cache()
+    # the FP64 oracle of 512^3 needs more host memory than the box holds: the
+    # error is stated on the 128^3 analogue (sphere radius 16), 20 steps, in
+    # the timed block shape, FP64 (the parity check: admissibility decided on
+    # the same inputs) and FP32 (populations can leave the admissible range
+    # at other cells than in FP64; the counts say how many)
+    small = wl.blast(128)
+    res["error_vs_oracle_128"] = {
+        "fp64": live_error(torch, rlb, small, 20, rlb.FP64, variant),
+        "fp32": live_error(torch, rlb, small, 20, rlb.FP32, variant)}
     return res
 
 
-def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50):
+def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
+                  oracle_L: int = 64, oracle_steps: int = 200):
+    """The adjoint form on the L x L x 1 shear-wave/vortex field, FP32, with
+    checkpoints every K steps. The loss is the L2 mismatch of the final u and
+    eps with a target made by the same model (FP64) at seeded perturbed
+    relaxation times plus 1 % noise. Times (HIP events on the handle's
+    stream): the taped forward, and the gradient (rlb_grad) after one untimed
+    call that instantiates its graph. Errors: dL/dtau against central finite
+    differences of the FP64 forward (h = 1e-4), over max(|FD|, |grad|); and
+    every output against the oracle's FP64 adjoint on the oracle_L^2 instance,
+    oracle_steps steps."""
+    import copy
     import numpy as np
+    import oracle
     prob = wl.shear_vortex(L)
     p = prob.params
-    try:
-        sim = rlb.from_problems(prob, precision=rlb.FP32, ckpt_every=K, tape_steps=steps)
-    except rlb.RLBError as e:
-        return {"status": str(e)}
+    nc = p.ncells
+
+    def fields_fp64(q):
+        sim = rlb.from_problems(q, precision=rlb.FP64)
+        sim.step(steps)
+        m = sim.moments()
+        out = (m["u"].cpu().numpy(), m["eps"].cpu().numpy())
+        sim.close()
+        return out
+
+    def with_tau(**kw):
+        q = copy.deepcopy(prob)
+        for k, v in kw.items():
+            setattr(q.params, k, v)
+        return q
+
+    tv, te, tpe = wl.perturbed_taus((p.tau_v, p.tau_e, p.tau_eps), seed=1212)
+    ut, et = fields_fp64(with_tau(tau_v=tv, tau_e=te, tau_eps=tpe))
+    z = wl.target_noise(prob.eps.shape, seed=1212).reshape(4, nc)
+    ut = ut + 0.01 * np.sqrt((ut ** 2).mean()) * z[:3]
+    et = et + 0.01 * np.sqrt((et ** 2).mean()) * z[3]
+
+    def loss(u, e):
+        return float(((u - ut) ** 2).sum() + ((e - et) ** 2).sum())
+
+    sim = rlb.from_problems(prob, precision=rlb.FP32, ckpt_every=K, tape_steps=steps)
+    stream = sim.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    ev[0].record(stream)
     sim.step(steps)
+    ev[1].record(stream)
     m = sim.moments()
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    gen = torch.Generator(device=sim.device).manual_seed(1212)
-    du = torch.randn(3, sim.ncells, dtype=torch.float64, device=sim.device, generator=gen) * 1e-2
-    de = torch.randn(sim.ncells, dtype=torch.float64, device=sim.device, generator=gen) * 1e-2
+    u, e = m["u"].cpu().numpy(), m["eps"].cpu().numpy()
+    du = torch.from_numpy(2.0 * (u - ut)).to(sim.device)
+    de = torch.from_numpy(2.0 * (e - et)).to(sim.device)
     t0 = time.perf_counter()
-    try:
-        dtau, de0, du0 = sim.grad(du, de)
-    except rlb.RLBError as e:
-        return {"status": str(e), "forward_s": t_fwd}
+    sim.grad(du, de)  # builds and instantiates the reverse sweep's graph
+    first_s = time.perf_counter() - t0
     torch.cuda.synchronize()
-    t_bwd = time.perf_counter() - t0
-    cells = sim.ncells
-    return {"lattice": f"{L}x{L}x1", "steps": steps, "ckpt_every": K, "forward_s": t_fwd,
-            "gradient_s": t_bwd, "cell_steps_per_s": cells * steps / (t_fwd + t_bwd),
+    ev[2].record(stream)
+    dtau, de0, du0 = sim.grad(du, de)
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    grad_ms = ev[2].elapsed_time(ev[3])
+    sim.close()
+    h = 1e-4
+    fd = []
+    for name in ("tau_v", "tau_e", "tau_eps"):
+        t0 = getattr(p, name)
+        lp = loss(*fields_fp64(with_tau(**{name: t0 + h})))
+        lm = loss(*fields_fp64(with_tau(**{name: t0 - h})))
+        fd.append((lp - lm) / (2.0 * h))
+    fd = np.array(fd)
+    scale = max(np.abs(fd).max(), np.abs(dtau).max())
+    # the oracle's FP64 adjoint on a small instance of the same generator
+    small = wl.shear_vortex(oracle_L, seed=1212)
+    rng = np.random.default_rng(6)
+    sdu, sde = rng.normal(size=small.u.shape), rng.normal(size=small.eps.shape)
+    s2 = rlb.from_problems(small, precision=rlb.FP32, ckpt_every=K, tape_steps=oracle_steps)
+    s2.step(oracle_steps)
+    g_tau, g_e0, g_u0 = s2.grad(torch.from_numpy(sdu.reshape(3, -1)),
+                                torch.from_numpy(sde.reshape(-1)))
+    s2.close()
+    o_tau, o_e0, o_u0 = oracle.grad(small, oracle_steps, sdu, sde)
+
+    def rel(a, b):
+        a, b = np.asarray(a).ravel(), np.asarray(b).ravel()
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    cell_steps = nc * steps
+    total_ms = fwd_ms + grad_ms
+    return {"lattice": f"{L}x{L}x1", "steps": steps, "ckpt_every": K,
+            "forward_ms": fwd_ms, "gradient_ms": grad_ms,
+            "gradient_first_call_s": first_s,
+            "cell_steps_per_s": cell_steps / (total_ms * 1e-3),
             "bytes_per_cell_step": 684,
-            "effective_gbs": 684 * cells * steps / (t_fwd + t_bwd) / 1e9,
-            "dL_dtau": [float(x) for x in dtau]}
+            "achieved_gbs": 684 * cell_steps / (total_ms * 1e-3) / 1e9,
+            "frac": 684 * cell_steps / (total_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "gradient_reverse_gbs": 380 * cell_steps / (grad_ms * 1e-3) / 1e9,
+            "graph_launches_per_gradient": 1,
+            "loss": loss(u, e), "dL_dtau": [float(x) for x in dtau],
+            "dL_dtau_fd": [float(x) for x in fd],
+            "error_vs_fd": float(np.abs(dtau - fd).max() / scale),
+            "error_vs_oracle_adjoint": {"lattice": f"{oracle_L}x{oracle_L}x1",
+                                        "steps": oracle_steps, "dL_dtau": rel(g_tau, o_tau),
+                                        "dL_deps0": rel(g_e0.cpu().numpy(), o_e0),
+                                        "dL_du0": rel(g_u0.cpu().numpy(), o_u0)}}
 
 
 def tile_traffic(kernel: str, nx: int, ny: int, cell_bytes: int, corr: int):
@@ -259,16 +483,30 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
         tiles = tile_traffic(tune["name"], n, n, bpc // 2, corr)
         if tiles:
             # tile rounds move fewer bytes than one step's 2 x 18 values per
-            # cell update: bytes_per_cell, achieved_gbs and frac count the
-            # round's own traffic (window read + owned write per H steps), and
-            # the one-step equivalent is kept beside them
-            tiles["hbm_gbs"] = tiles["hbm_bytes_per_cell_update"] * cells / (ms * 1e-3) / 1e9
-            out[name].update({"bytes_per_cell": tiles["hbm_bytes_per_cell_update"],
-                              "achieved_gbs": tiles["hbm_gbs"],
-                              "frac": tiles["hbm_gbs"] / HBM_PEAK_GBS,
-                              "one_step_equivalent_gbs": gbs,
-                              "one_step_equivalent_frac": gbs / HBM_PEAK_GBS})
+            # cell update: achieved_gbs and frac count the round's own HBM
+            # traffic, measured by the byte counters when the committed record
+            # matches these sources, else the model (window read + owned write
+            # per H steps); the bound is the VALU issue rate when the committed
+            # VALU record holds this kernel
+            meas = measured_d2q9(tune["name"])
+            bpu = meas["bytes_per_cell_update"] if meas else tiles["hbm_bytes_per_cell_update"]
+            tiles["hbm_bytes_per_cell_update_source"] = "counters" if meas else "model"
+            out[name].update({"bytes_per_cell": bpu,
+                              "achieved_gbs": bpu * cells / (ms * 1e-3) / 1e9,
+                              "frac": bpu * cells / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS})
             out[name]["tile_rounds"] = tiles
+            valu = measured_valu(tune["name"])
+            if valu:
+                rate = valu["valu_per_cell_update"] * cells / (ms * 1e-3) / 1e9
+                out[name]["alu_roofline"] = {
+                    "bound": "alu", "achieved": rate, "peak": VALU_PEAK_GINST, "unit": "Ginst/s",
+                    "frac": rate / VALU_PEAK_GINST,
+                    "note": "VALU wave-instructions per cell update (SQ_INSTS_VALU) x cell "
+                            "updates per second, against one wave-instruction per CU and cycle"}
+        # the timed variant against the oracle: one tile round (3 steps) of the
+        # whole lattice
+        out[name]["error_vs_oracle"] = live_error(torch, rlb, prob, 3, prec, tune["name"],
+                                                  diag_every=50, correction=corr)
         sim.close()
     del prob
     cases = [wl.qgp_tube_2d(c) for c in "ABCD"]
@@ -290,8 +528,9 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
         out[name] = {"members": " ".join(c.name for c in batch), "steps": 400,
                      "ms_total": ms, "us_per_step": 1e3 * ms / 400,
                      "mlups": nc * 400 / (ms * 1e-3) / 1e6, "kernel": tune["name"],
-                     "inadmissible": sim.moments()["bad"]}
+                     **graph_shape(tune["name"], 400), "inadmissible": sim.moments()["bad"]}
         sim.close()
+        out[name]["error_vs_oracle"] = live_error(torch, rlb, batch, 400, prec, tune["name"])
     return out
 
 
@@ -312,6 +551,7 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
            "mlups": cells / (ms * 1e-3) / 1e6, "kernel": tune["name"], "achieved_gbs": gbs,
            "frac": gbs / HBM_PEAK_GBS}
     sim.close()
+    out["error_vs_oracle"] = live_error(torch, rlb, prob, 2, rlb.FP32, tune["name"])
     # the same lattice under P = (Gamma - 1)(eps - m n): Newton recovery per cell
     prob.params.eta_s = 0.0
     prob.params.eos_gamma, prob.params.mass = 1.5, 0.6
@@ -323,6 +563,8 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
                           "mlups": cells / (ms * 1e-3) / 1e6, "kernel": tune["name"],
                           "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
     sim.close()
+    out["general_eos"]["error_vs_oracle"] = live_error(torch, rlb, prob, 2, rlb.FP32,
+                                                       tune["name"])
     del prob
     tubes = [wl.qgp_tube_3d(0.1, tau_f=tf) for tf in ("tau_g", 1.0, 0.6)]
     sim = rlb.from_problems(tubes, precision=rlb.FP64)
@@ -335,8 +577,11 @@ def bench_eta_s(torch, rlb, wl, n: int = 256, steps: int = 50, warmup: int = 5):
     e1.record()
     torch.cuda.synchronize()
     out["sec3_tube_batch"] = {"members": "3 x (1x1x800), tau_f = tau_g, 1.0, 0.6", "steps": 400,
-                              "ms_total": e0.elapsed_time(e1), "kernel": tune["name"]}
+                              "ms_total": e0.elapsed_time(e1), "kernel": tune["name"],
+                              **graph_shape(tune["name"], 400)}
     sim.close()
+    out["sec3_tube_batch"]["error_vs_oracle"] = live_error(torch, rlb, tubes, 400, rlb.FP64,
+                                                           tune["name"])
     return out
 
 
@@ -595,12 +840,48 @@ def valu_summary(csv_path: str, command: str) -> str:
     return "\n".join(out) + "\n"
 
 
+def d2q9_kernel_name(kernel: str, grid: int, n: int = 4096):
+    """(variant name, steps per launch) of a D2Q9 lattice-path dispatch on the
+    n x n periodic lattice, from the mangled-template name in a rocprofv3
+    record and its grid (threads): k_d2q9_lattice<T, BX, BY, CY, DIAG, CORR,
+    EXT, NTS>, k_d2q9_lattice_c7<T, BX, BY, DIAG, EXT, NTS> (one step a
+    launch) and k_d2q9_tiles<T, TX, TY, NTH, CORR, EXT> (H steps a launch,
+    H recovered from the number of tiles in the grid). None for launches
+    with fused diagnostics, the extended model, or other kernels."""
+    m = re.search(r"k_d2q9_tiles<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+)", kernel)
+    if m:
+        typ, tx, ty, nth, corr, ext = m.groups()
+        if ext == "true":
+            return None
+        tx, ty, nth = int(tx), int(ty), int(nth)
+        tiles = grid // nth
+        c = corr == "true"
+        H = next((h for h in range(1, 9)
+                  if -(-n // (tx - 2 * h)) * -(-n // (ty - 2 * (2 * h if c else h))) == tiles),
+                 None)
+        if H is None:
+            return None
+        return f"k_d2q9_tiles<{typ},{tx},{ty}>/h{H}" + ("+c7" if c else ""), H
+    m = re.search(r"k_d2q9_lattice<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+), (\w+)", kernel)
+    if m:
+        typ, bx, by, cy, diag, corr, ext = m.groups()
+        if diag == "true" or ext == "true":
+            return None
+        return f"k_d2q9_lattice<{typ},{bx},{by},{cy}>" + ("+c7" if corr == "true" else ""), 1
+    m = re.search(r"k_d2q9_lattice_c7<(\w+), (\d+), (\d+), (\w+), (\w+)", kernel)
+    if m:
+        typ, bx, by, diag, ext = m.groups()
+        if diag == "true" or ext == "true":
+            return None
+        return f"k_d2q9_lattice<{typ},{bx},{by},1>+c7", 1
+    return None
+
+
 def d2q9_traffic(fetch_csv: str, write_csv: str, n: int = 4096) -> dict:
     """HBM bytes of the D2Q9 lattice-path kernels on the n x n lattice from two
-    PMC runs (FETCH_SIZE, WRITE_SIZE), scaled as in write_traffic: per launch
-    for the one-step kernels (against 2 x 18 values per cell), and per cell
-    update for the tile rounds, whose launches advance H steps (H recovered
-    from the number of tiles in the launch grid)."""
+    PMC runs (FETCH_SIZE, WRITE_SIZE), scaled as in write_traffic: per launch,
+    and per cell update (a tile-round launch advances H steps), against the
+    one-step 2 x 18 values per cell."""
     import collections
     import csv
     vals = collections.defaultdict(list)
@@ -613,42 +894,40 @@ def d2q9_traffic(fetch_csv: str, write_csv: str, n: int = 4096) -> dict:
     scale = {c: (1 << 30) / copy[c] for c in copy}
     recs = collections.defaultdict(dict)
     for (k, g, c), v in vals.items():
-        m = re.search(r"k_d2q9_(lattice|tiles)<(\w+), (\d+), (\d+), (\d+), (\w+), (\w+)", k)
-        if m:
-            kind, typ, a1, a2, a3, f1, f2 = m.groups()
-        else:
-            # k_d2q9_lattice_c7<T, BX, BY, DIAG, EXT, NTS>: one cell a thread, CORR
-            m = re.search(r"k_d2q9_lattice_c7<(\w+), (\d+), (\d+), (\w+), (\w+)", k)
-            if not m:
-                continue
-            typ, a1, a2, f1, _ = m.groups()
-            kind, a3, f2 = "lattice", "1", "true"
-        recs[(kind, typ, int(a1), int(a2), int(a3), f1, f2, g)][c] = sum(v) / len(v) * scale[c]
+        nm = d2q9_kernel_name(k, g, n)
+        if nm:
+            recs[nm][c] = sum(v) / len(v) * scale[c]
     cells = n * n
-    out = {"lattice": f"{n}x{n}", "calibration": scale, "kernels": {}}
-    for (kind, typ, a1, a2, a3, f1, f2, g), r in sorted(recs.items()):
+    out = {"lattice": f"{n}x{n}", "calibration": scale, "source_hash": kernel_hash(D2Q9_SOURCES),
+           "kernels": {}}
+    for (name, H), r in sorted(recs.items()):
         if "FETCH_SIZE" not in r or "WRITE_SIZE" not in r:
             continue
-        esz = 4 if typ == "float" else 8
+        esz = 4 if "float" in name else 8
         total = r["FETCH_SIZE"] + r["WRITE_SIZE"]
-        if kind == "lattice":  # <T, BX, BY, CY, DIAG, CORR, EXT>
-            if f1 == "true":
-                continue  # the launches with fused diagnostics
-            name = f"k_d2q9_lattice<{typ},{a1},{a2},{a3}>" + ("+c7" if f2 == "true" else "")
-            out["kernels"][name] = {"bytes_per_launch": total,
-                                    "ratio": total / (2 * 18 * esz * cells)}
-        else:  # <T, TX, TY, NTH, CORR, EXT>
-            tiles = g // a3
-            corr = f1 == "true"
-            H = next((h for h in range(1, 9)
-                      if -(-n // (a1 - 2 * h)) * -(-n // (a2 - 2 * (2 * h if corr else h)))
-                      == tiles), None)
-            if H is None:
-                continue
-            name = f"k_d2q9_tiles<{typ},{a1},{a2}>/h{H}" + ("+c7" if corr else "")
-            out["kernels"][name] = {"bytes_per_launch": total,
-                                    "bytes_per_cell_update": total / (cells * H),
-                                    "one_step_bytes_per_cell_update": 2 * 18 * esz}
+        out["kernels"][name] = {"bytes_per_launch": total, "steps_per_launch": H,
+                                "bytes_per_cell_update": total / (cells * H),
+                                "one_step_bytes_per_cell_update": 2 * 18 * esz,
+                                "ratio_to_one_step": total / (cells * H) / (2 * 18 * esz)}
+    return out
+
+
+def valu_record(csv_path: str, n: int = 4096) -> dict:
+    """VALU wave-instructions per cell update of the D2Q9 lattice-path kernels
+    on the n x n lattice, from the same PMC run as valu_summary."""
+    import collections
+    import csv
+    vals = collections.defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] != "SQ_INSTS_VALU":
+            continue
+        nm = d2q9_kernel_name(r["Kernel_Name"], int(r["Grid_Size"]), n)
+        if nm:
+            vals[nm].append(float(r["Counter_Value"]))
+    out = {"lattice": f"{n}x{n}", "source_hash": kernel_hash(D2Q9_SOURCES), "kernels": {}}
+    for (name, H), v in sorted(vals.items()):
+        out["kernels"][name] = {"valu_per_launch": sum(v) / len(v), "steps_per_launch": H,
+                                "valu_per_cell_update": sum(v) / len(v) / (n * n * H)}
     return out
 
 
@@ -667,7 +946,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="only the headline FP32 step")
     ap.add_argument("--forms", default="",
                     help="comma list of the forms to run besides the headline (default: all): "
-                         "fp64, batched, adjoint, blast_512, d2q9, eta_s, copy_ceiling")
+                         "fp64, shock_tube, batched, adjoint, blast_512, d2q9, eta_s, "
+                         "copy_ceiling")
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--diag-every", type=int, default=50,
                     help="fuse the FP64 conservation sums into every N-th step")
@@ -676,9 +956,11 @@ def main():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--valu-summary", nargs=2, metavar=("CSV", "COMMAND"),
-                    help="print the VALU load of the step kernels from one PMC run and exit")
+                    help="print the VALU load of the step kernels from one PMC run (and write "
+                         "profiles/valu_d2q9.json for the D2Q9 kernels it holds) and exit")
     ap.add_argument("--d2q9-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="print the HBM bytes of the D2Q9 kernels from two PMC runs and exit")
+                    help="write profiles/traffic_d2q9.json (HBM bytes of the D2Q9 kernels) from "
+                         "two PMC runs and exit")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two PMC runs and exit")
     args = ap.parse_args()
@@ -689,10 +971,17 @@ def main():
         print(json.dumps(cpu_baseline_sweep()), flush=True)
         return
     if args.d2q9_traffic:
-        print(json.dumps(d2q9_traffic(*args.d2q9_traffic), indent=1))
+        rec = d2q9_traffic(*args.d2q9_traffic)
+        with open(D2Q9_TRAFFIC_FILE, "w") as fh:
+            json.dump(rec, fh, indent=1, sort_keys=True)
+        print(json.dumps(rec, indent=1, sort_keys=True))
         return
     if args.valu_summary:
         print(valu_summary(*args.valu_summary), end="")
+        rec = valu_record(args.valu_summary[0])
+        if rec["kernels"]:
+            with open(VALU_FILE, "w") as fh:
+                json.dump(rec, fh, indent=1, sort_keys=True)
         return
     if args.write_traffic:
         rec = write_traffic(*args.write_traffic)
@@ -738,8 +1027,9 @@ def main():
                                           "kernel", "conservation_drift")}
         forms[oname]["traffic"] = measured_traffic(o["kernel"], o["cells"])
         log("other precision", forms)
-    runs = (("batched", bench_batched), ("adjoint", bench_adjoint), ("blast_512", bench_blast),
-            ("d2q9", bench_d2q9), ("eta_s", bench_eta_s))
+    runs = (("shock_tube", bench_shock_tube), ("batched", bench_batched),
+            ("adjoint", bench_adjoint), ("blast_512", bench_blast), ("d2q9", bench_d2q9),
+            ("eta_s", bench_eta_s))
     for name, fn in runs:
         if want(name):
             forms[name] = fn(torch, rlb, wl)

@@ -178,6 +178,12 @@ rlb_status rlb_init(rlb_handle* out, const rlb_params* members, int32_t n_member
                     size_t workspace_bytes, void* hip_stream);
 
 /* Advance every member by nsteps >= 0 steps, asynchronously on the stream.
+ * One step of a cell is the update of Sec. II and V.A: streaming, the left-
+ * hand side of Eqs. (5), (6) and (35) (pull from x - e_a); the moments of
+ * Eq. (10) and the recovery of (n, eps, P, gamma, u) from them; the
+ * equilibria of Eqs. (7)-(9) (D2Q9: Eqs. 32-34); the f BGK collision of
+ * Eq. (5) and the g MRT collision of Eqs. (30)-(31), m* = m - S(m - m_eq),
+ * g* = M^-1 m* (Eq. 35), with the correction of Eq. (37) when selected.
  * Single-member lattices run one fused kernel launch per step (D2Q9: or
  * rounds of H steps on tiles held in LDS); batches (and small single
  * lattices) run in a HIP graph, either all nsteps inside one persistent

@@ -10,7 +10,9 @@
 // in the interior, up to four at clamped corners, never an atomic), applies
 // the transposed collision Jacobian (adjoint_cell.hpp) and writes 19 values:
 // 3 x 19 populations of traffic per cell-step. dL/dtau is accumulated in FP64
-// per block across all steps and reduced once at the end.
+// per block across all steps and reduced once at the end. The whole reverse
+// sweep is one HIP graph in which the recomputation of the next segment runs
+// beside the reverse steps of the current one (two segment buffers).
 
 #include <hip/hip_runtime.h>
 
@@ -136,34 +138,51 @@ __global__ __launch_bounds__(256) void k_adj_loss(const T* __restrict__ state, i
 // One reverse step. state: g*(t) (the step's input); adj_in: either the
 // adjoint of g*(t+1) (GATHER = false, straight from the loss) or the
 // pre-collision adjoint of step t+1 (GATHER = true, transposed streaming
-// applied here). adj_out: pre-collision adjoint of step t.
-template <typename T, bool GATHER>
+// applied here). adj_out: pre-collision adjoint of step t. Each thread takes
+// CPT cells NT apart, reading all their forward and adjoint populations
+// before the arithmetic of the first.
+template <typename T, bool GATHER, int CPT>
 __global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
                                                   const T* __restrict__ adj_in,
                                                   T* __restrict__ adj_out, int64_t cs,
                                                   MemberDesc d, double* __restrict__ partials) {
   const uint32_t esz = sizeof(T);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
-    int x, y, z;
-    decompose(c, d, x, y, z);
-    uint32_t off[19], self;
-    pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self);
-    T g[19], gb[19];
+  for (int c0 = blockIdx.x * (256 * CPT) + threadIdx.x; c0 < d.ncells;
+       c0 += gridDim.x * (256 * CPT)) {
+    AdjPrep<T> pr[CPT];
+    T gb[CPT][19];
+    uint32_t self[CPT];
 #pragma unroll
-    for (int a = 0; a < 19; ++a) g[a] = ld(state + (int64_t)a * cs, off[a]);
-    if (GATHER) {
-      gather_adjoint(adj_in, cs, x, y, z, d, gb);
-    } else {
+    for (int k = 0; k < CPT; ++k) {
+      // a cell past the end repeats the last one and is not stored
+      const int c = min(c0 + 256 * k, d.ncells - 1);
+      int x, y, z;
+      decompose(c, d, x, y, z);
+      uint32_t off[19];
+      pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self[k]);
+      T g[19];
 #pragma unroll
-      for (int a = 0; a < 19; ++a) gb[a] = adj_in[(int64_t)a * cs + c];
+      for (int a = 0; a < 19; ++a) g[a] = ld(state + (int64_t)a * cs, off[a]);
+      if (GATHER) {
+        gather_adjoint(adj_in, cs, x, y, z, d, gb[k]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 19; ++a) gb[k][a] = adj_in[(int64_t)a * cs + c];
+      }
+      adjoint_prepare(g, d.ref, pr[k]);
     }
-    double dt[4] = {0.0, 0.0, 0.0, 0.0};
-    cell_adjoint(g, gb, d.rt, d.ref, dt);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) acc[k] += dt[k];
+    for (int k = 0; k < CPT; ++k) {
+      double dt[4] = {0.0, 0.0, 0.0, 0.0};
+      adjoint_apply(pr[k], gb[k], d.rt, dt);
+      if (c0 + 256 * k < d.ncells) {
 #pragma unroll
-    for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self, gb[a]);
+        for (int q = 0; q < 4; ++q) acc[q] += dt[q];
+#pragma unroll
+        for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self[k], gb[k][a]);
+      }
+    }
   }
   block_sum5<256>(acc, threadIdx.x);
   if (threadIdx.x == 0)
@@ -207,6 +226,125 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* parts, int n, d
     for (int k = 0; k < 5; ++k) out[k] = v[k];
 }
 
+void release_graph(Tape& t) {
+  if (t.graph_exec) (void)hipGraphExecDestroy(t.graph_exec);
+  if (t.graph) (void)hipGraphDestroy(t.graph);
+  t.graph_exec = nullptr;
+  t.graph = nullptr;
+  t.graph_steps = -1;
+}
+
+// Cells per thread of the reverse step. Two cells a thread fill a 512 x 512
+// step in one round of waves (188 VGPRs, 2 waves per SIMD) instead of 1.33
+// rounds of one-cell waves (159 VGPRs, 3 per SIMD), but measured no faster.
+constexpr int kAdjCPT = 1;
+
+dim3 adj_grid(int64_t ncells) {
+  int64_t b = (ncells + 256 * kAdjCPT - 1) / (256 * kAdjCPT);
+  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
+}
+
+// Adds one kernel node after the given dependencies.
+template <typename... A>
+hipError_t add_node(hipGraph_t g, hipGraphNode_t* out, const hipGraphNode_t* deps, int ndeps,
+                    const void* func, dim3 grid, dim3 block, A... args) {
+  void* params[] = {(void*)&args...};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(func);
+  kp.gridDim = grid;
+  kp.blockDim = block;
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = params;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(out, g, ndeps ? deps : nullptr, ndeps, &kp);
+}
+
+// The reverse sweep over every checkpointed segment, last first, as one HIP
+// graph of kernel nodes: per segment k, the g-only recomputation of its
+// states from checkpoint k (chain G(k)), then one reverse step per step of
+// the segment (chain R(k)). Segments alternate between two state buffers, so
+// that G(k-1) runs beside R(k), as a parallel branch of the graph: G(k-1)
+// waits only for R(k+1), the last reader of its buffer, and R(k) for G(k)
+// and R(k+1). The graph depends only on the step count and the tape's
+// buffers: it is built once per step count and kept with the tape.
+template <typename T>
+rlb_status chain_graph(Tape& t, const GradContext& c) {
+  const TapeLayout& L = t.L;
+  const MemberDesc d = c.desc;
+  const int64_t cs = c.cs;
+  const int64_t T_steps = c.steps;
+  const int K = L.K;
+  const dim3 grid(grid_of(c.ncells)), agrid(adj_grid(c.ncells)), block(256);
+  auto ckpt = [&](int64_t k) { return (const T*)(t.base + L.off_ckpt + (size_t)k * L.gbytes); };
+  auto seg = [&](int64_t k, int64_t j) {
+    return (T*)(t.base + L.off_seg + (size_t)((k & 1) * K + j) * L.gbytes);
+  };
+  T* adj[2] = {(T*)(t.base + L.off_adj), (T*)(t.base + L.off_adj + L.gbytes)};
+  double* parts = (double*)(t.base + L.off_tparts);
+  hipGraph_t g = nullptr;
+  if (hipGraphCreate(&g, 0) != hipSuccess) return RLB_E_DEVICE;
+  hipError_t e = hipSuccess;
+  // G(k) after dep (null: no dependency); *last = its last node (null when
+  // the segment has a single step and nothing to recompute)
+  auto add_G = [&](int64_t k, hipGraphNode_t dep, hipGraphNode_t* last) {
+    const int64_t t0 = k * K;
+    const int64_t t1 = std::min<int64_t>(t0 + K, T_steps);
+    const T* src = ckpt(k);
+    hipGraphNode_t prev = dep;
+    *last = nullptr;
+    for (int64_t tt = t0 + 1; tt < t1 && e == hipSuccess; ++tt) {
+      T* dst = seg(k, tt - t0);
+      hipGraphNode_t n;
+      e = add_node(g, &n, &prev, prev ? 1 : 0, (const void*)&k_gstep<T>, grid, block, src, dst,
+                   cs, d);
+      prev = *last = n;
+      src = dst;
+    }
+  };
+  int cur = 0;
+  bool gathered = false;
+  const int64_t kmax = (T_steps - 1) / K;
+  hipGraphNode_t lastG = nullptr, lastR = nullptr;
+  add_G(kmax, nullptr, &lastG);
+  for (int64_t k = kmax; k >= 0 && e == hipSuccess; --k) {
+    const int64_t t0 = k * K;
+    const int64_t t1 = std::min<int64_t>(t0 + K, T_steps);
+    hipGraphNode_t nextG = nullptr;
+    if (k > 0) add_G(k - 1, lastR, &nextG);  // beside R(k): after R(k+1) only
+    hipGraphNode_t deps[2];
+    int nd = 0;
+    if (lastG) deps[nd++] = lastG;
+    if (lastR) deps[nd++] = lastR;
+    hipGraphNode_t prev = nullptr;
+    for (int64_t tt = t1 - 1; tt >= t0 && e == hipSuccess; --tt) {
+      const T* st = (tt == t0) ? ckpt(k) : (const T*)seg(k, tt - t0);
+      const T* in = adj[cur];
+      T* out = adj[1 - cur];
+      const void* f = gathered ? (const void*)&k_adj_step<T, true, kAdjCPT>
+                               : (const void*)&k_adj_step<T, false, kAdjCPT>;
+      hipGraphNode_t n;
+      e = prev ? add_node(g, &n, &prev, 1, f, agrid, block, st, in, out, cs, d, parts)
+               : add_node(g, &n, deps, nd, f, agrid, block, st, in, out, cs, d, parts);
+      prev = n;
+      cur = 1 - cur;
+      gathered = true;
+    }
+    lastR = prev;
+    lastG = nextG;
+  }
+  hipGraphExec_t x = nullptr;
+  if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return RLB_E_DEVICE;
+  }
+  release_graph(t);
+  t.graph = g;
+  t.graph_exec = x;
+  t.graph_steps = T_steps;
+  return RLB_OK;
+}
+
 template <typename T>
 rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const double* dLdeps,
                     double dL_dtau[3], double* deps0, double* du0) {
@@ -214,48 +352,28 @@ rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const dou
   const MemberDesc d = c.desc;
   const int64_t cs = c.cs;
   const int64_t T_steps = c.steps;
-  const int K = L.K;
   hipStream_t s = c.stream;
-  const dim3 grid(grid_of(c.ncells)), block(256);
-  auto ckpt = [&](int64_t k) { return (T*)(t.base + L.off_ckpt + (size_t)k * L.gbytes); };
-  auto seg = [&](int64_t j) { return (T*)(t.base + L.off_seg + (size_t)j * L.gbytes); };
+  const dim3 grid(grid_of(c.ncells)), agrid(adj_grid(c.ncells)), block(256);
   T* adj[2] = {(T*)(t.base + L.off_adj), (T*)(t.base + L.off_adj + L.gbytes)};
   const double* f0 = (const double*)(t.base + L.off_fields);
   double* parts = (double*)(t.base + L.off_tparts);
-  if (hipMemsetAsync(parts, 0, sizeof(double) * 5 * (size_t)grid.x, s) != hipSuccess)
+  if (T_steps > 0 && (!t.graph_exec || t.graph_steps != T_steps)) {
+    const rlb_status st = chain_graph<T>(t, c);
+    if (st != RLB_OK) return st;
+  }
+  if (hipMemsetAsync(parts, 0, sizeof(double) * 5 * (size_t)agrid.x, s) != hipSuccess)
     return RLB_E_DEVICE;
   const T* final_g = (const T*)((const char*)c.state + 19 * (size_t)cs * sizeof(T));
   hipLaunchKernelGGL(k_adj_loss<T>, grid, block, 0, s, final_g, cs, d, dLdu, dLdeps, adj[0]);
-  int cur = 0;
-  bool gathered = false;
-  if (T_steps > 0) {
-    for (int64_t k = (T_steps - 1) / K; k >= 0; --k) {
-      const int64_t t0 = k * K;
-      const int64_t t1 = std::min<int64_t>(t0 + K, T_steps);
-      const T* prev = ckpt(k);
-      for (int64_t tt = t0 + 1; tt < t1; ++tt) {
-        hipLaunchKernelGGL(k_gstep<T>, grid, block, 0, s, prev, seg(tt - t0), cs, d);
-        prev = seg(tt - t0);
-      }
-      for (int64_t tt = t1 - 1; tt >= t0; --tt) {
-        const T* st = (tt == t0) ? ckpt(k) : seg(tt - t0);
-        if (gathered)
-          hipLaunchKernelGGL((k_adj_step<T, true>), grid, block, 0, s, st, adj[cur],
-                             adj[1 - cur], cs, d, parts);
-        else
-          hipLaunchKernelGGL((k_adj_step<T, false>), grid, block, 0, s, st, adj[cur],
-                             adj[1 - cur], cs, d, parts);
-        cur = 1 - cur;
-        gathered = true;
-      }
-    }
-  }
-  if (gathered)
+  if (T_steps > 0 && hipGraphLaunch(t.graph_exec, s) != hipSuccess) return RLB_E_DEVICE;
+  // the chain's last reverse step wrote adj[T_steps & 1]
+  const int cur = (int)(T_steps & 1);
+  if (T_steps > 0)
     hipLaunchKernelGGL((k_adj_init<T, true>), grid, block, 0, s, adj[cur], cs, d, f0, deps0, du0);
   else
     hipLaunchKernelGGL((k_adj_init<T, false>), grid, block, 0, s, adj[cur], cs, d, f0, deps0,
                        du0);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, parts, (int)grid.x, c.sums_out);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, parts, (int)agrid.x, c.sums_out);
   if (hipGetLastError() != hipSuccess) return RLB_E_DEVICE;
   double h[5];
   if (hipMemcpyAsync(h, c.sums_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -280,8 +398,8 @@ TapeLayout tape_layout(int64_t ncells, int64_t cs, size_t esz, int K, int tape_s
   size_t o = 0;
   L.off_ckpt = o;
   o = al(o + L.gbytes * L.n_ckpt);
-  L.off_seg = o;
-  o = al(o + L.gbytes * K);
+  L.off_seg = o;  // two segments' states: the one reversed, the next recomputed
+  o = al(o + L.gbytes * 2 * (size_t)K);
   L.off_adj = o;
   o = al(o + 2 * L.gbytes);
   L.off_fields = o;
@@ -353,6 +471,9 @@ rlb_status tape_grad(Tape& t, const GradContext& c, const double* dL_du, const d
   return RLB_OK;
 }
 
-void tape_release(Tape& t) { t.base = nullptr; }
+void tape_release(Tape& t) {
+  release_graph(t);
+  t.base = nullptr;
+}
 
 }  // namespace rlb

@@ -16,7 +16,7 @@ struct TapeLayout {
   int n_ckpt = 0;         // checkpoints at steps 0, K, 2K, ...
   int K = 0;
   size_t off_ckpt = 0;    // n_ckpt g states
-  size_t off_seg = 0;     // K g states of the segment being reversed
+  size_t off_seg = 0;     // 2K g states: the segment being reversed, the next recomputed
   size_t off_adj = 0;     // two adjoint g buffers
   size_t off_fields = 0;  // eps0, u0 (4 * ncells doubles)
   size_t off_tparts = 0;  // per-block tau-gradient partials (max_parts * 5 doubles)
@@ -32,6 +32,10 @@ struct Tape {
   TapeLayout L;
   int precision = 0;
   int64_t ncells = 0, cs = 0;
+  // the reverse sweep's kernel chain, instantiated for graph_steps steps
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int64_t graph_steps = -1;
 };
 
 rlb_status tape_init(Tape& t, const TapeLayout& L, char* base, int precision, int64_t ncells,
@@ -53,6 +57,6 @@ struct GradContext {
 
 rlb_status tape_grad(Tape& t, const GradContext& c, const double* dL_du, const double* dL_deps,
                      double dL_dtau[3], double* dL_deps0, double* dL_du0, int io_on_device);
-void tape_release(Tape& t);
+void tape_release(Tape& t);  // also destroys the kept graph
 
 }  // namespace rlb

@@ -16,35 +16,60 @@
 
 namespace rlb {
 
+// The recovery of cell.hpp with the intermediates its adjoint reuses:
+// r = sqrt(4 E^2 - 3 |M|^2), q = 3 / (2E + r) (u = q M), and
+// 1 / (3 + u^2) (sigma = 4 E / (3 + u^2)). Admissibility as in recover().
+struct Recovered {
+  Macro mac;
+  double r, q, inv_den;
+};
+
+__device__ __forceinline__ bool recover_keep(double E, double Mx, double My, double Mz,
+                                             Recovered& R) {
+  const double M2 = Mx * Mx + My * My + Mz * Mz;
+  const bool ok = (E > 0.0) && (M2 < E * E);
+  const double Es = ok ? E : 1.0;
+  const double M2s = ok ? M2 : 0.0;
+  R.r = sqrt(4.0 * Es * Es - 3.0 * M2s);
+  R.q = 3.0 / (2.0 * Es + R.r);
+  Macro& m = R.mac;
+  m.ux = ok ? R.q * Mx : 0.0;
+  m.uy = ok ? R.q * My : 0.0;
+  m.uz = ok ? R.q * Mz : 0.0;
+  m.u2 = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+  R.inv_den = 1.0 / (3.0 + m.u2);
+  m.sigma = 4.0 * Es * R.inv_den;
+  m.P = 0.25 * m.sigma * (1.0 - m.u2);
+  return ok;
+}
+
 // Adjoint of the recovery. In: the bars of sigma, P, u. Out: bars of E, M.
 __device__ __forceinline__ void recovery_adjoint(double E, double Mx, double My, double Mz,
-                                                 const Macro& mac, double sb, double Pb,
+                                                 const Recovered& R, double sb, double Pb,
                                                  double ubx, double uby, double ubz, double& Eb,
                                                  double& Mbx, double& Mby, double& Mbz) {
+  const Macro& mac = R.mac;
   // P = sigma (1 - u^2) / 4
   sb += 0.25 * (1.0 - mac.u2) * Pb;
   ubx -= 0.5 * mac.sigma * mac.ux * Pb;
   uby -= 0.5 * mac.sigma * mac.uy * Pb;
   ubz -= 0.5 * mac.sigma * mac.uz * Pb;
   // sigma = 4 E / (3 + u^2)
-  const double den = 3.0 + mac.u2;
-  Eb = 4.0 * sb / den;
-  const double t = -2.0 * mac.sigma * sb / den;
+  Eb = 4.0 * sb * R.inv_den;
+  const double t = -2.0 * mac.sigma * sb * R.inv_den;
   ubx += t * mac.ux;
   uby += t * mac.uy;
   ubz += t * mac.uz;
-  // u = q M, q = 3 / D, D = 2E + r, r = sqrt(4 E^2 - 3 |M|^2)
-  const double M2 = Mx * Mx + My * My + Mz * Mz;
-  const double r = sqrt(4.0 * E * E - 3.0 * M2);
-  const double D = 2.0 * E + r;
-  const double q = 3.0 / D;
+  // u = q M, q = 3 / D, D = 2E + r: dq/dD = -q^2 / 3, dr/dE = 4E / r, dr/dM = -3M / r
+  const double q = R.q;
   Mbx = q * ubx;
   Mby = q * uby;
   Mbz = q * ubz;
   const double qb = ubx * Mx + uby * My + ubz * Mz;
-  const double Db = -qb * q / D;
-  Eb += 2.0 * Db + Db * 4.0 * E / r;
-  const double rm = -3.0 * Db / r;
+  const double Db = -qb * q * q * (1.0 / 3.0);
+  const double inv_r = 1.0 / R.r;
+  Eb += 2.0 * Db + Db * 4.0 * E * inv_r;
+  const double rm = -3.0 * Db * inv_r;
   Mbx += rm * Mx;
   Mby += rm * My;
   Mbz += rm * Mz;
@@ -75,25 +100,44 @@ __device__ __forceinline__ void equilibrium_adjoint(const NonConserved<C>& l, co
          s * (lyz * uy + lxz * ux);
 }
 
-// gbar[a] += aE + e_a . aM
+// gbar[a] += aE + e_a . aM, in the precision of the adjoint populations (the
+// four terms are rounded to it first).
 template <typename C>
 __device__ __forceinline__ void add_scalar_vector(C (&gb)[19], double aE, double ax, double ay,
                                                   double az) {
+  const C e0 = (C)aE, cx = (C)ax, cy = (C)ay, cz = (C)az;
 #pragma unroll
-  for (int a = 0; a < 19; ++a) gb[a] = gb[a] + (C)(aE + ex(a) * ax + ey(a) * ay + ez(a) * az);
+  for (int a = 0; a < 19; ++a)
+    gb[a] = gb[a] + (e0 + C(ex(a)) * cx + C(ey(a)) * cy + C(ez(a)) * cz);
 }
 
-// Reverse of one g collision. g: the cell's stored pre-collision populations;
+// Reverse of one g collision, in two phases so that the step kernel can read
+// the forward populations of several cells before their adjoints. g: the
+// cell's stored pre-collision populations; adjoint_prepare keeps what the
+// reverse needs of them (sums, recovery, the non-equilibrium moments d).
+template <typename C>
+struct AdjPrep {
+  double E, Mx, My, Mz;
+  Recovered rec;
+  NonConserved<C> d;
+  bool ok;
+};
+
+template <typename C>
+__device__ __forceinline__ void adjoint_prepare(const C (&g)[19], const Ref& ref, AdjPrep<C>& p) {
+  double gs;
+  g_sums(g, ref, p.E, p.Mx, p.My, p.Mz, gs);
+  p.ok = recover_keep(p.E, p.Mx, p.My, p.Mz, p.rec);
+  p.d = nc_sub(moments_nc(g), equilibrium_nc<C>(p.rec.mac, ref));
+}
+
 // gb: in gbar*, out gbar (pre-collision). dtau accumulates dL/dtau for the
 // rate groups (v, e, eps, q). An inadmissible cell was not collided: identity.
 template <typename C>
-__device__ __forceinline__ void cell_adjoint(const C (&g)[19], C (&gb)[19], const Rates& rt,
-                                             const Ref& ref, double (&dtau)[4]) {
-  double E, Mx, My, Mz, gs;
-  g_sums(g, ref, E, Mx, My, Mz, gs);
-  Macro mac;
-  if (!recover(E, Mx, My, Mz, mac)) return;
-  const NonConserved<C> d = nc_sub(moments_nc(g), equilibrium_nc<C>(mac, ref));
+__device__ __forceinline__ void adjoint_apply(const AdjPrep<C>& p, C (&gb)[19], const Rates& rt,
+                                              double (&dtau)[4]) {
+  if (!p.ok) return;
+  const NonConserved<C>& d = p.d;
   const NonConserved<C> mb = moments_nc(gb);
   const NonConserved<C> lam = scale_rates(mb, rt);
   // dL/dtau_k = mb_k d_k s_k^2 / |row_k|^2
@@ -112,9 +156,9 @@ __device__ __forceinline__ void cell_adjoint(const C (&g)[19], C (&gb)[19], cons
                     ((double)mb.mx * (double)d.mx + (double)mb.my * (double)d.my +
                      (double)mb.mz * (double)d.mz) / kNormM);
   double sb = 0.0, Pb = 0.0, ubx = 0.0, uby = 0.0, ubz = 0.0;
-  equilibrium_adjoint(lam, mac, sb, Pb, ubx, uby, ubz);
+  equilibrium_adjoint(lam, p.rec.mac, sb, Pb, ubx, uby, ubz);
   double aE, ax, ay, az;
-  recovery_adjoint(E, Mx, My, Mz, mac, sb, Pb, ubx, uby, ubz, aE, ax, ay, az);
+  recovery_adjoint(p.E, p.Mx, p.My, p.Mz, p.rec, sb, Pb, ubx, uby, ubz, aE, ax, ay, az);
   sub_MT(gb, lam);
   add_scalar_vector(gb, aE, ax, ay, az);
 }
@@ -127,17 +171,18 @@ __device__ __forceinline__ void loss_adjoint(const C (&g)[19], const Ref& ref, d
                                              C (&gb)[19]) {
   double E, Mx, My, Mz, gs;
   g_sums(g, ref, E, Mx, My, Mz, gs);
-  Macro mac;
+  Recovered R;
 #pragma unroll
   for (int a = 0; a < 19; ++a) gb[a] = C(0.0);
-  if (!recover(E, Mx, My, Mz, mac)) return;
+  if (!recover_keep(E, Mx, My, Mz, R)) return;
+  const Macro& mac = R.mac;
   // eps = (3/4) sigma (1 - u^2)
   const double sb = 0.75 * (1.0 - mac.u2) * deps;
   const double ubx = dux - 1.5 * mac.sigma * mac.ux * deps;
   const double uby = duy - 1.5 * mac.sigma * mac.uy * deps;
   const double ubz = duz - 1.5 * mac.sigma * mac.uz * deps;
   double aE, ax, ay, az;
-  recovery_adjoint(E, Mx, My, Mz, mac, sb, 0.0, ubx, uby, ubz, aE, ax, ay, az);
+  recovery_adjoint(E, Mx, My, Mz, R, sb, 0.0, ubx, uby, ubz, aE, ax, ay, az);
   add_scalar_vector(gb, aE, ax, ay, az);
 }
 

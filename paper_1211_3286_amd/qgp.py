@@ -11,18 +11,16 @@ Relaxation times follow from the ratio eta/s (Sec. III.B): the entropy
 density is s = 4n - n ln(lambda), lambda = n / n_eq, n_eq = d_G T^3 / pi^2
 (d_G = 16 for gluons), and the viscosity relation after Eq. (10),
 eta = (tau - 1/2) c_s^2 (eps + P) gamma, gives
-tau = 1/2 + kappa (eta/s) s / (c_s^2 (eps + P) gamma). kappa is the
-transformation of the shear viscosity the model needs for (1+1)-dimensional
-flows: 1 for the plain relation of Sec. III, 2/3 for the BGK model in 3D
-(Sec. IV: 2 eta in place of 4 eta / 3) and 4/3 for the D2Q9 MRT model with a
-small bulk viscosity (Sec. V.A, Eq. 36 with D = 2). The kernels evaluate the
-same relation per cell (rlb_params.eta_over_s); this module gives the values
-for chosen states, e.g. to pick fixed relaxation times.
+tau = 1/2 + kappa (eta/s) s / (c_s^2 (eps + P) gamma), which the kernels
+evaluate per cell (rlb_params.eta_over_s). kappa is the transformation of the
+shear viscosity the model needs for (1+1)-dimensional flows: 1 for the plain
+relation of Sec. III, 2/3 for the BGK model in 3D (Sec. IV: 2 eta in place of
+4 eta / 3) and 4/3 for the D2Q9 MRT model with a small bulk viscosity
+(Sec. V.A, Eq. 36 with D = 2); this module holds those constants and the unit
+conversions only.
 """
 
 from __future__ import annotations
-
-import math
 
 DX_FM = 3.2 / 400.0  # lattice spacing and time step, fm (and fm/c)
 E_UNIT_GEV = 0.350 / 0.0314  # energy unit: 350 MeV is 0.0314
@@ -48,18 +46,3 @@ def lattice_density(n_per_fm3: float) -> float:
 
 def time_fm(steps: float) -> float:
     return steps * DX_FM
-
-
-def entropy_density(n: float, T: float, dof: float = DOF_GLUONS) -> float:
-    """s = 4n - n ln(n / n_eq), n_eq = dof T^3 / pi^2 (lattice units)."""
-    n_eq = dof * T ** 3 / math.pi ** 2
-    return 4.0 * n - n * math.log(n / n_eq)
-
-
-def tau_from_eta_s(eta_s: float, n: float, P: float, gamma: float = 1.0,
-                   kappa: float = KAPPA_PLAIN, dof: float = DOF_GLUONS) -> float:
-    """Shear relaxation time of a state (n, P = eps/3, gamma) at ratio eta/s."""
-    T = P / n
-    eta = eta_s * entropy_density(n, T, dof)
-    sigma = 4.0 * P * gamma * gamma  # (eps + P) gamma^2 with eps = 3P
-    return 0.5 + kappa * eta / (CS2 * sigma / gamma)

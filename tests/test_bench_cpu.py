@@ -103,8 +103,42 @@ def test_d2q9_traffic_names_both_corrected_kernels(tmp_path):
     _write(tmp_path / "w.csv", write)
     out = bench.d2q9_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), n=n)["kernels"]
     assert sorted(out) == ["k_d2q9_lattice<float,128,2,1>+c7", "k_d2q9_lattice<float,64,8,1>+c7"]
-    assert abs(out["k_d2q9_lattice<float,128,2,1>+c7"]["ratio"] - 1.0) < 1e-12
-    assert abs(out["k_d2q9_lattice<float,64,8,1>+c7"]["ratio"] - 1.25) < 1e-12
+    assert abs(out["k_d2q9_lattice<float,128,2,1>+c7"]["ratio_to_one_step"] - 1.0) < 1e-12
+    assert abs(out["k_d2q9_lattice<float,64,8,1>+c7"]["ratio_to_one_step"] - 1.25) < 1e-12
+
+
+def test_d2q9_tile_rounds_priced_per_cell_update(tmp_path):
+    """A tile-round launch advances H steps: its bytes and VALU instructions
+    per cell update divide by the cells and by H, which is recovered from the
+    number of tiles in the launch grid."""
+    n = 4096
+    cells = n * n
+    kib = 1024.0
+    # 32 x 32 window, H = 3: owned 26 x 26, ceil(4096 / 26) = 158 tiles a side
+    tiles = 158 * 158
+    k = ("void rlb::(anonymous namespace)::k_d2q9_tiles<float, 32, 32, 512, false, "
+         "false>(rlb::TileRound)")
+    fetch = [(COPY, "131072", "FETCH_SIZE", (1 << 29) / kib),
+             (k, str(tiles * 512), "FETCH_SIZE", 56.0 * cells * 3 / 2 / 2 / kib)]
+    write = [(COPY, "131072", "WRITE_SIZE", (1 << 30) / kib),
+             (k, str(tiles * 512), "WRITE_SIZE", 56.0 * cells * 3 / 2 / kib)]
+    _write(tmp_path / "f.csv", fetch)
+    _write(tmp_path / "w.csv", write)
+    out = bench.d2q9_traffic(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), n=n)["kernels"]
+    rec = out["k_d2q9_tiles<float,32,32>/h3"]
+    assert rec["steps_per_launch"] == 3
+    assert abs(rec["bytes_per_cell_update"] - 56.0) < 1e-9
+    _write(tmp_path / "v.csv", [(k, str(tiles * 512), "SQ_INSTS_VALU", 7.0 * cells * 3)])
+    v = bench.valu_record(str(tmp_path / "v.csv"), n=n)["kernels"]
+    assert abs(v["k_d2q9_tiles<float,32,32>/h3"]["valu_per_cell_update"] - 7.0) < 1e-12
+
+
+def test_graph_shape_counts_the_kernel_nodes():
+    assert bench.graph_shape("k_step_tubes<float,256>/h8", 3000) == {
+        "graph_launches": 1, "kernel_nodes": 375, "steps_per_node": 8}
+    assert bench.graph_shape("k_d2q9_strips<double,256>/h8", 400)["kernel_nodes"] == 50
+    assert bench.graph_shape("k_step_members<float,512,1>", 3000) == {
+        "graph_launches": 1, "kernel_nodes": 1, "steps_per_node": 3000}
 
 
 def test_more_than_one_gpu_is_refused_before_any_device_work():

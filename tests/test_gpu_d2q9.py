@@ -134,6 +134,21 @@ def test_periodic_conservation(prec):
     assert step == 240 and relmax(d, s1) < (1e-13 if prec == FP64 else 1e-10)
 
 
+def test_fp32_conservation_at_the_bar():
+    """The conserved-sum bar of 1e-10 itself, in FP32, on a lattice large
+    enough for the rounding random walk (about 1e-8 sqrt(T / cells)) to stay
+    below it: 1024 x 1024 for 100 steps, in the variant the autotuner picks."""
+    prob = _problem(1024, 1024, (0, 0, 0))
+    sim = gpu_run(prob, 0, FP32, diag_every=50)
+    res = sim.tune(trial_steps=6)
+    s0 = sim.sums()
+    sim.step(100)
+    s1 = sim.sums()
+    drift = np.abs(s1 - s0).max() / np.abs(s0[:2]).max()
+    say("d2q9 fp32 conservation 1024^2 x 100,", res["name"], "drift", drift)
+    assert drift < 1e-10
+
+
 def test_host_pointer_populations_and_validation():
     import ctypes
     import torch

@@ -86,6 +86,47 @@ def test_random_flow_256cubed(prec, tol):
     assert drift < (1e-10 if prec == FP32 else 1e-13)  # periodic: conserved
 
 
+@pytest.mark.timeout(900)
+def test_random_flow_fp32_at_500_steps_all_cells():
+    """The headline workload's stated length: FP32 populations after all 500
+    steps, against the FP64 oracle over every cell, on a 128^3 instance of the
+    same generator (the oracle runs the 256^3 lattice at about 20 MLUPS on the
+    host: 128^3 x 500 steps takes about a minute), in the block shape the
+    benchmark times at 256^3 and in the one-cell-per-thread shape."""
+    import torch
+    import paper_1211_3286_amd as rlb
+    prob = wl.random_modes(128, seed=1211, umax=0.1, amp=0.05, tau_v=0.8, tau_e=0.55,
+                           tau_eps=0.7, tau_f=0.8)
+    T = 500
+    say("random flow 128^3, FP32, 500 steps, every cell; oracle first")
+    st = oracle.State.init(prob)
+    for t in range(0, T, 50):
+        st.step(50)
+        say("  oracle step", t + 50)
+    F = st.fields()
+    for name in ("k_step_lattice<float,64,4,1>", "k_step_lattice<float,256,1,1>"):
+        sim = rlb.from_problems(prob, precision=FP32)
+        sim.variant = sim.variants().index(name)
+        s0 = sim.sums()
+        sim.step(T)
+        s1 = sim.sums()
+        f, g = sim.populations()
+        m = sim.moments()
+        sh = prob.params.shape
+        err = {"f": relmax(f.cpu().numpy().reshape((19,) + sh), st.f),
+               "g": relmax(g.cpu().numpy().reshape((19,) + sh), st.g),
+               "n": relmax(m["n"].cpu().numpy().reshape(sh), F["n"]),
+               "eps": relmax(m["eps"].cpu().numpy().reshape(sh), F["eps"]),
+               "u": float(np.abs(m["u"].cpu().numpy().reshape((3,) + sh) - F["u"]).max())}
+        drift = np.abs(s1 - s0).max() / np.abs(s0[:2]).max()
+        say(" ", name, "max-norm errors after 500 steps", err, "sum drift", drift)
+        sim.close()
+        del f, g, m
+        torch.cuda.empty_cache()
+        assert max(err.values()) < 1e-5 and st.bad == 0
+        assert drift < 1e-10
+
+
 # Cells on the lattice diagonals of the velocity shell, where the 100:1 blast
 # leaves the admissible range (E <= 0 or |M| >= E) within two steps; the
 # oracle finds the same cells inadmissible on its windows.
