@@ -35,11 +35,60 @@ int grid_of(int64_t n) {
   return (int)b;
 }
 
-__device__ __forceinline__ void decompose(int c, const MemberDesc& d, int& x, int& y, int& z) {
+// What the reverse-sweep kernels read of the lattice (a small argument, held
+// in scalar registers): shape, boundaries, relaxation rates and reference.
+struct AdjGeom {
+  int32_t nx, ny, nz, bcx, bcy, bcz;
+  Rates rt;
+  Ref ref;
+};
+
+AdjGeom adj_geom(const MemberDesc& d) {
+  AdjGeom g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.nz = d.nz;
+  g.bcx = d.bcx;
+  g.bcy = d.bcy;
+  g.bcz = d.bcz;
+  g.rt = d.rt;
+  g.ref = d.ref;
+  return g;
+}
+
+template <typename G>
+__device__ __forceinline__ void decompose(int c, const G& d, int& x, int& y, int& z) {
   x = c % d.nx;
   const int yz = c / d.nx;
   y = yz % d.ny;
   z = yz / d.ny;
+}
+
+// The step kernels' geometry: each wave takes 64 consecutive x-cells of one
+// row (y, z), a block kRows rows, one cell per thread (the grid's y and z
+// count blocks of rows). The row index is uniform in a wave, so (y, z) come
+// from a scalar division and no cell index is divided; with no loop over
+// cells the reverse step fits 115 VGPRs (4 waves per SIMD: a 512 x 512 step
+// in one round of waves).
+constexpr int kRows = 4;
+constexpr int64_t kMaxGridY = 65535;
+
+dim3 row_grid(const AdjGeom& g) {
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  const int64_t nrb = (rows + kRows - 1) / kRows;
+  const int64_t gy = std::min(nrb, kMaxGridY);
+  return dim3((unsigned)((g.nx + 63) / 64), (unsigned)gy, (unsigned)((nrb + gy - 1) / gy));
+}
+
+int64_t row_blocks(const AdjGeom& g) {
+  const dim3 r = row_grid(g);
+  return (int64_t)r.x * r.y * r.z;
+}
+
+// The row of this thread (uniform in its wave).
+__device__ __forceinline__ int thread_row() {
+  return __builtin_amdgcn_readfirstlane(
+      (int)((blockIdx.z * gridDim.y + blockIdx.y) * kRows + threadIdx.y));
 }
 
 // Cells y with src(y, e) = c along one axis (the pull source is y - e,
@@ -70,9 +119,9 @@ __device__ __forceinline__ int preimages(int c, int e, int N, int bc, int (&out)
 // walk the preimage sets per axis.
 __device__ __forceinline__ int opposite(int a) { return a == 0 ? 0 : ((a & 1) ? a + 1 : a - 1); }
 
-template <typename T>
+template <typename T, typename G>
 __device__ __forceinline__ void gather_adjoint(const T* __restrict__ adj, int64_t cs, int x, int y,
-                                               int z, const MemberDesc& d, T (&gb)[19]) {
+                                               int z, const G& d, T (&gb)[19]) {
   const bool face = (d.bcx && (x == 0 || x == d.nx - 1)) ||
                     (d.bcy && (y == 0 || y == d.ny - 1)) ||
                     (d.bcz && (z == 0 || z == d.nz - 1));
@@ -102,11 +151,12 @@ __device__ __forceinline__ void gather_adjoint(const T* __restrict__ adj, int64_
 // g-only forward step between g-plane buffers (recomputation of a segment).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gstep(const T* __restrict__ src, T* __restrict__ dst,
-                                               int64_t cs, MemberDesc d) {
+                                               int64_t cs, AdjGeom d) {
   const uint32_t esz = sizeof(T);
-  for (int c = blockIdx.x * 256 + threadIdx.x; c < d.ncells; c += gridDim.x * 256) {
-    int x, y, z;
-    decompose(c, d, x, y, z);
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int r = thread_row();
+  if (x < d.nx && r < d.ny * d.nz) {
+    const int y = r % d.ny, z = r / d.ny;
     uint32_t off[19], self;
     pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self);
     T g[19];
@@ -138,56 +188,50 @@ __global__ __launch_bounds__(256) void k_adj_loss(const T* __restrict__ state, i
 // One reverse step. state: g*(t) (the step's input); adj_in: either the
 // adjoint of g*(t+1) (GATHER = false, straight from the loss) or the
 // pre-collision adjoint of step t+1 (GATHER = true, transposed streaming
-// applied here). adj_out: pre-collision adjoint of step t. Each thread takes
-// CPT cells NT apart, reading all their forward and adjoint populations
-// before the arithmetic of the first.
-template <typename T, bool GATHER, int CPT>
+// applied here). adj_out: pre-collision adjoint of step t. Row geometry of
+// k_gstep; dL/dtau partials per block.
+template <typename T, bool GATHER>
 __global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
                                                   const T* __restrict__ adj_in,
-                                                  T* __restrict__ adj_out, int64_t cs,
-                                                  MemberDesc d, double* __restrict__ partials) {
+                                                  T* __restrict__ adj_out, int64_t cs, AdjGeom d,
+                                                  double* __restrict__ partials) {
   const uint32_t esz = sizeof(T);
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  for (int c0 = blockIdx.x * (256 * CPT) + threadIdx.x; c0 < d.ncells;
-       c0 += gridDim.x * (256 * CPT)) {
-    AdjPrep<T> pr[CPT];
-    T gb[CPT][19];
-    uint32_t self[CPT];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      // a cell past the end repeats the last one and is not stored
-      const int c = min(c0 + 256 * k, d.ncells - 1);
-      int x, y, z;
-      decompose(c, d, x, y, z);
-      uint32_t off[19];
-      pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self[k]);
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int r = thread_row();
+  if (x < d.nx && r < d.ny * d.nz) {
+    const int y = r % d.ny, z = r / d.ny;
+    uint32_t off[19], self;
+    pull_offsets(x, y, z, d.nx, d.ny, d.nz, d.bcx, d.bcy, d.bcz, 0u, esz, off, self);
+    AdjPrep<T> pr;
+    {
       T g[19];
 #pragma unroll
       for (int a = 0; a < 19; ++a) g[a] = ld(state + (int64_t)a * cs, off[a]);
-      if (GATHER) {
-        gather_adjoint(adj_in, cs, x, y, z, d, gb[k]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < 19; ++a) gb[k][a] = adj_in[(int64_t)a * cs + c];
-      }
-      adjoint_prepare(g, d.ref, pr[k]);
+      adjoint_prepare(g, d.ref, pr);
     }
+    T gb[19];
+    if (GATHER) {
+      gather_adjoint(adj_in, cs, x, y, z, d, gb);
+    } else {
+      const int64_t c = (int64_t)r * d.nx + x;
 #pragma unroll
-    for (int k = 0; k < CPT; ++k) {
-      double dt[4] = {0.0, 0.0, 0.0, 0.0};
-      adjoint_apply(pr[k], gb[k], d.rt, dt);
-      if (c0 + 256 * k < d.ncells) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += dt[q];
-#pragma unroll
-        for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self[k], gb[k][a]);
-      }
+      for (int a = 0; a < 19; ++a) gb[a] = adj_in[(int64_t)a * cs + c];
     }
+    double dt[4] = {0.0, 0.0, 0.0, 0.0};
+    adjoint_apply(pr, gb, d.rt, dt);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += dt[q];
+#pragma unroll
+    for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self, gb[a]);
   }
-  block_sum5<256>(acc, threadIdx.x);
-  if (threadIdx.x == 0)
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  block_sum5<256>(acc, tid);
+  if (tid == 0)
 #pragma unroll
-    for (int k = 0; k < 5; ++k) partials[(int64_t)blockIdx.x * 5 + k] += acc[k];
+    for (int k = 0; k < 5; ++k)
+      partials[(((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 5 + k] +=
+          acc[k];
 }
 
 // dL/deps0, dL/du0 from the adjoint of the initial state.
@@ -234,16 +278,6 @@ void release_graph(Tape& t) {
   t.graph_steps = -1;
 }
 
-// Cells per thread of the reverse step. Two cells a thread fill a 512 x 512
-// step in one round of waves (188 VGPRs, 2 waves per SIMD) instead of 1.33
-// rounds of one-cell waves (159 VGPRs, 3 per SIMD), but measured no faster.
-constexpr int kAdjCPT = 1;
-
-dim3 adj_grid(int64_t ncells) {
-  int64_t b = (ncells + 256 * kAdjCPT - 1) / (256 * kAdjCPT);
-  return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536)));
-}
-
 // Adds one kernel node after the given dependencies.
 template <typename... A>
 hipError_t add_node(hipGraph_t g, hipGraphNode_t* out, const hipGraphNode_t* deps, int ndeps,
@@ -270,11 +304,11 @@ hipError_t add_node(hipGraph_t g, hipGraphNode_t* out, const hipGraphNode_t* dep
 template <typename T>
 rlb_status chain_graph(Tape& t, const GradContext& c) {
   const TapeLayout& L = t.L;
-  const MemberDesc d = c.desc;
+  const AdjGeom d = adj_geom(c.desc);
   const int64_t cs = c.cs;
   const int64_t T_steps = c.steps;
   const int K = L.K;
-  const dim3 grid(grid_of(c.ncells)), agrid(adj_grid(c.ncells)), block(256);
+  const dim3 grid(row_grid(d)), block(64, kRows);
   auto ckpt = [&](int64_t k) { return (const T*)(t.base + L.off_ckpt + (size_t)k * L.gbytes); };
   auto seg = [&](int64_t k, int64_t j) {
     return (T*)(t.base + L.off_seg + (size_t)((k & 1) * K + j) * L.gbytes);
@@ -320,11 +354,11 @@ rlb_status chain_graph(Tape& t, const GradContext& c) {
       const T* st = (tt == t0) ? ckpt(k) : (const T*)seg(k, tt - t0);
       const T* in = adj[cur];
       T* out = adj[1 - cur];
-      const void* f = gathered ? (const void*)&k_adj_step<T, true, kAdjCPT>
-                               : (const void*)&k_adj_step<T, false, kAdjCPT>;
+      const void* f = gathered ? (const void*)&k_adj_step<T, true>
+                               : (const void*)&k_adj_step<T, false>;
       hipGraphNode_t n;
-      e = prev ? add_node(g, &n, &prev, 1, f, agrid, block, st, in, out, cs, d, parts)
-               : add_node(g, &n, deps, nd, f, agrid, block, st, in, out, cs, d, parts);
+      e = prev ? add_node(g, &n, &prev, 1, f, grid, block, st, in, out, cs, d, parts)
+               : add_node(g, &n, deps, nd, f, grid, block, st, in, out, cs, d, parts);
       prev = n;
       cur = 1 - cur;
       gathered = true;
@@ -353,7 +387,8 @@ rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const dou
   const int64_t cs = c.cs;
   const int64_t T_steps = c.steps;
   hipStream_t s = c.stream;
-  const dim3 grid(grid_of(c.ncells)), agrid(adj_grid(c.ncells)), block(256);
+  const dim3 grid(grid_of(c.ncells)), block(256);
+  const int nparts = (int)row_blocks(adj_geom(d));
   T* adj[2] = {(T*)(t.base + L.off_adj), (T*)(t.base + L.off_adj + L.gbytes)};
   const double* f0 = (const double*)(t.base + L.off_fields);
   double* parts = (double*)(t.base + L.off_tparts);
@@ -361,7 +396,7 @@ rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const dou
     const rlb_status st = chain_graph<T>(t, c);
     if (st != RLB_OK) return st;
   }
-  if (hipMemsetAsync(parts, 0, sizeof(double) * 5 * (size_t)agrid.x, s) != hipSuccess)
+  if (hipMemsetAsync(parts, 0, sizeof(double) * 5 * (size_t)nparts, s) != hipSuccess)
     return RLB_E_DEVICE;
   const T* final_g = (const T*)((const char*)c.state + 19 * (size_t)cs * sizeof(T));
   hipLaunchKernelGGL(k_adj_loss<T>, grid, block, 0, s, final_g, cs, d, dLdu, dLdeps, adj[0]);
@@ -373,7 +408,7 @@ rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const dou
   else
     hipLaunchKernelGGL((k_adj_init<T, false>), grid, block, 0, s, adj[cur], cs, d, f0, deps0,
                        du0);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, parts, (int)agrid.x, c.sums_out);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, parts, nparts, c.sums_out);
   if (hipGetLastError() != hipSuccess) return RLB_E_DEVICE;
   double h[5];
   if (hipMemcpyAsync(h, c.sums_out, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -388,13 +423,18 @@ rlb_status run_grad(Tape& t, const GradContext& c, const double* dLdu, const dou
 
 }  // namespace
 
-TapeLayout tape_layout(int64_t ncells, int64_t cs, size_t esz, int K, int tape_steps,
+TapeLayout tape_layout(int nx, int ny, int nz, int64_t cs, size_t esz, int K, int tape_steps,
                        int max_parts) {
   TapeLayout L;
+  const int64_t ncells = (int64_t)nx * ny * nz;
+  AdjGeom g{};
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
   L.K = K;
   L.gbytes = 19 * (size_t)cs * esz;
   L.n_ckpt = tape_steps / K + 1;
-  L.max_parts = max_parts;
+  L.max_parts = (int)std::max<int64_t>(max_parts, row_blocks(g));  // reverse-step partials
   size_t o = 0;
   L.off_ckpt = o;
   o = al(o + L.gbytes * L.n_ckpt);
@@ -405,7 +445,7 @@ TapeLayout tape_layout(int64_t ncells, int64_t cs, size_t esz, int K, int tape_s
   L.off_fields = o;
   o = al(o + sizeof(double) * 4 * (size_t)ncells);
   L.off_tparts = o;
-  o = al(o + sizeof(double) * 5 * (size_t)max_parts);
+  o = al(o + sizeof(double) * 5 * (size_t)L.max_parts);
   L.total = o;
   return L;
 }

@@ -24,7 +24,7 @@ struct TapeLayout {
   int max_parts = 0;
 };
 
-TapeLayout tape_layout(int64_t ncells, int64_t cs, size_t esz, int K, int tape_steps,
+TapeLayout tape_layout(int nx, int ny, int nz, int64_t cs, size_t esz, int K, int tape_steps,
                        int max_parts);
 
 struct Tape {

@@ -26,6 +26,8 @@ constexpr size_t kAlign = 256;
 constexpr int64_t kLatticeMinCells = 16384;
 // Double-buffered states up to this size are stored with plain stores.
 constexpr size_t kCachedStateBytes = size_t(1) << 30;
+// Pad after each population plane (see make_layout).
+constexpr int64_t kPlanePadBytes = 1280;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -124,10 +126,11 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
     for (int i = 0; i < n; ++i)
       if (!paper_eos(m[i])) return RLB_E_UNSUPPORTED;  // C_7 is derived for P = eps/3
   L.esz = opt->precision == RLB_FP32 ? 4 : 8;
-  // Plane stride: a multiple of 64 elements plus 64 more, so that planes of a
-  // power-of-two lattice do not all start on the same HBM channel (measured:
-  // about 3 % faster at 256^3 than unpadded planes).
-  L.cs = (L.ncells + 63) / 64 * 64 + 64;
+  // Plane stride: a multiple of 64 elements plus 1280 bytes, so that planes of
+  // a power-of-two lattice do not all start alike on the HBM channels
+  // (measured: 3-5 % faster at 256^3 than unpadded planes in both precisions,
+  // and at 512^3 FP32 2 % faster than a 256-byte pad).
+  L.cs = (L.ncells + 63) / 64 * 64 + kPlanePadBytes / (int64_t)L.esz;
   // every population byte offset of a plane is a 32-bit quantity in the kernels
   if ((uint64_t)L.cs * L.esz >= (uint64_t(1) << 32)) return RLB_E_UNSUPPORTED;
   int parts = std::max<int64_t>(n, (L.ncells + 255) / 256 > 65536 ? 65536 : (L.ncells + 255) / 256);
@@ -185,8 +188,8 @@ rlb_status make_layout(const rlb_params* m, int32_t n, const rlb_options* opt, L
   o = align_up(o + sizeof(unsigned long long) * (size_t)L.max_segs);
   L.off_tape = o;
   if (opt->ckpt_every > 0) {
-    L.tape = rlb::tape_layout(L.ncells, L.cs, L.esz, opt->ckpt_every, opt->tape_steps,
-                              L.max_parts);
+    L.tape = rlb::tape_layout(m[0].nx, m[0].ny, m[0].nz, L.cs, L.esz, opt->ckpt_every,
+                              opt->tape_steps, L.max_parts);
     o = align_up(o + L.tape.total);
   }
   L.total = o;
