@@ -7,6 +7,8 @@ per-member kernel), both precisions, ragged tails and mixed boundaries; the
 Tolerances (max-norm relative): FP64 1e-12, FP32 1e-5.
 """
 
+import re
+
 import numpy as np
 import pytest
 
@@ -409,11 +411,12 @@ def test_tile_rounds_identical_to_one_step_kernel(shape, prec, corr):
         try:
             s2.step(T)
         except rlb.RLBError as e:
-            # refused: a 64 x 8 window leaves no owned row with the 2H halo of
-            # the correction term; FP64 with the correction term does not fit
-            # a 1024-cell window in LDS
-            big = ",32,32>" in name or ",64,16>" in name
-            assert e.code == -7 and corr and (",64,8>" in name or (prec == FP64 and big)), name
+            # refused: a window that leaves no owned row with the 2H halo of
+            # the correction term (64 x 8, and 32 x 16 at H = 4); FP64 with the
+            # correction term does not fit a 1024-cell window in LDS
+            tx, ty, h = (int(v) for v in re.search(r",(\d+),(\d+)>/h(\d+)", name).groups())
+            no_rows = ty - 4 * h < 1
+            assert e.code == -7 and corr and (no_rows or (prec == FP64 and tx * ty == 1024)), name
             s2.close()
             continue
         f, g = [t.cpu().numpy() for t in s2.populations()]
