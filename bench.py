@@ -746,10 +746,22 @@ def summarize_trace(csv_path: str, command: str, top: int = 25, min_launches: in
     return "\n".join(out) + "\n"
 
 
-def write_traffic(fetch_csv: str, write_csv: str, cells: int = 256 ** 3) -> dict:
-    """HBM bytes per dispatch of every step-kernel variant from two PMC runs
-    (FETCH_SIZE, WRITE_SIZE in KiB), each scaled by what the same counter
-    reads for the 1 GiB plain copy of --copy-calibration."""
+def write_traffic(*csvs: str, cells: int = 256 ** 3) -> dict:
+    """HBM bytes per dispatch of every step-kernel variant from pairs of PMC
+    runs (FETCH_SIZE, WRITE_SIZE in KiB; e.g. one pair per precision), each
+    counter scaled by what it reads for the 1 GiB plain copy of
+    --copy-calibration in the same run."""
+    if len(csvs) < 2 or len(csvs) % 2:
+        raise ValueError("write_traffic takes FETCH_SIZE / WRITE_SIZE csv pairs")
+    out = {}
+    for i in range(0, len(csvs), 2):
+        rec = _traffic_pair(csvs[i], csvs[i + 1], cells)
+        out["_calibration" + ("" if i == 0 else f"_run{i // 2}")] = rec.pop("_calibration")
+        out.update(rec)
+    return out
+
+
+def _traffic_pair(fetch_csv: str, write_csv: str, cells: int) -> dict:
     import collections
     import csv
     vals = collections.defaultdict(list)
@@ -961,8 +973,9 @@ def main():
     ap.add_argument("--d2q9-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic_d2q9.json (HBM bytes of the D2Q9 kernels) from "
                          "two PMC runs and exit")
-    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two PMC runs and exit")
+    ap.add_argument("--write-traffic", nargs="+", metavar="CSV",
+                    help="write profiles/traffic.json from FETCH_SIZE / WRITE_SIZE csv pairs "
+                         "(one pair per PMC run pair) and exit")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
