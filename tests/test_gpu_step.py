@@ -29,6 +29,15 @@ SHAPES = [
 ]
 
 
+# Conserved sums of FP32-stored populations against the oracle's FP64 ones.
+# Storing a population in FP32 rounds it by at most 2^-24 (6.0e-8) of itself,
+# and the populations here are positive, so each sum of the stored values
+# differs from the FP64 sum by at most 2^-24 of the largest sum: the bound
+# is that, with 1.7x for the FP64 summation orders. Conservation over time
+# (the GPU's sums against its own initial sums) has its own 1e-10 bar.
+FP32_SUMS = 1e-7
+
+
 def _problem(nx, ny, nz, bc, seed=7):
     return wl.random_modes(nx, ny, nz, seed=seed, umax=0.2, amp=0.1, tau_v=0.8, tau_e=0.55,
                            tau_eps=0.7, tau_f=0.63, bc=bc)
@@ -50,7 +59,7 @@ def test_init_and_export_match_oracle(prec):
     assert relmax(gs["eps"], prob.eps) < ftol
     assert relmax(gs["n"], prob.n) < ftol
     assert np.abs(gs["u"] - prob.u).max() < ftol
-    assert relmax(sums, F["sums"]) < (1e-13 if prec == FP64 else 1e-7)
+    assert relmax(sums, F["sums"]) < (1e-13 if prec == FP64 else FP32_SUMS)
     assert bad == 0
 
 
@@ -71,7 +80,7 @@ def test_step_matches_oracle(prec, shape):
     assert bad == 0 and st.bad == 0
     assert err["f"] < TOL[prec] and err["g"] < TOL[prec], err
     assert err["eps"] < TOL[prec] and err["n"] < TOL[prec] and err["u"] < TOL[prec], err
-    assert relmax(sums, F["sums"]) < (1e-13 if prec == FP64 else 1e-7)
+    assert relmax(sums, F["sums"]) < (1e-13 if prec == FP64 else FP32_SUMS)
 
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
