@@ -451,7 +451,7 @@ def tile_traffic(kernel: str, nx: int, ny: int, cell_bytes: int, corr: int):
     read = tiles * tx * ty * cell_bytes
     write = nx * ny * cell_bytes
     return {"window": [tx, ty], "owned": [ox, oy], "steps_per_launch": h,
-            "hbm_bytes_per_cell_update": (read + write) / (nx * ny * h)}
+            "model_bytes_per_cell_update": (read + write) / (nx * ny * h)}
 
 
 def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10):
@@ -489,7 +489,8 @@ def bench_d2q9(torch, rlb, wl, n: int = 4096, steps: int = 100, warmup: int = 10
             # per H steps); the bound is the VALU issue rate when the committed
             # VALU record holds this kernel
             meas = measured_d2q9(tune["name"])
-            bpu = meas["bytes_per_cell_update"] if meas else tiles["hbm_bytes_per_cell_update"]
+            bpu = meas["bytes_per_cell_update"] if meas else tiles["model_bytes_per_cell_update"]
+            tiles["hbm_bytes_per_cell_update"] = bpu
             tiles["hbm_bytes_per_cell_update_source"] = "counters" if meas else "model"
             out[name].update({"bytes_per_cell": bpu,
                               "achieved_gbs": bpu * cells / (ms * 1e-3) / 1e9,
