@@ -491,6 +491,17 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
     const int pj0 = CORR && Y.left == kEdgeHalo ? j0 - 1 : j0;
     const int pj1 = CORR && Y.right == kEdgeHalo ? j1 + 1 : j1;
     const int w = i1 - i0, n = w * (pj1 - pj0);
+    // row of slot r: r / w through the hardware FP32 reciprocal (within 1 ulp
+    // of 1/w). (r + 1/2) / w lies at least 1/(2w) from an integer; the
+    // reciprocal's error and the product's rounding move it by at most 2^-22
+    // of itself, under 2^-11 for r < 2^11, which is less than 1/(2w) for
+    // w <= 256: the truncation is exact, in 3 instructions per slot where an
+    // integer division takes about 25
+    static_assert(NT <= 2048 && TX <= 256, "the reciprocal row split needs r < 2^11, w <= 256");
+    const float inv_w = __builtin_amdgcn_rcpf((float)w);
+    // owned range in window coordinates
+    const int oi0 = X.own0 - X.w0, oi1 = X.own1 - X.w0;
+    const int oj0 = Y.own0 - Y.w0, oj1 = Y.own1 - Y.w0;
     // every pull of the step lands in registers before the in-place writes
     T f[CPT][9], g[CPT][9];
     d2q9::Recovered rec[CPT];  // with CORR: the recovery behind the published fields
@@ -502,7 +513,7 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
       cell[k] = cm[k] = cp[k] = 0;
       upd[k] = own[k] = false;
       if (r < n) {
-        const int jr = r / w;
+        const int jr = (int)(((float)r + 0.5f) * inv_w);
         const int i = i0 + (r - jr * w), j = pj0 + jr;
         int im = i - 1, ip = i + 1, jm = j - 1, jp = j + 1;
         if (im < 0) im = X.left == kEdgeWrap ? X.wlen - 1 : 0;
@@ -521,8 +532,7 @@ __global__ __launch_bounds__(NTH) void k_d2q9_tiles(TileRound a) {
         cm[k] = jm * TX + i;  // C_7 neighbours
         cp[k] = jp * TX + i;
         upd[k] = j >= j0 && j < j1;
-        own[k] = X.w0 + i >= X.own0 && X.w0 + i < X.own1 && Y.w0 + j >= Y.own0 &&
-                 Y.w0 + j < Y.own1;
+        own[k] = i >= oi0 && i < oi1 && j >= oj0 && j < oj1;
         if constexpr (CORR) {
           rec[k] = d2q9::recovered<T, EXT>(f[k], g[k], a.ref, &a.ext);
           const d2q9::C7Fields F = d2q9::c7_fields(rec[k].mac, rec[k].ok);
