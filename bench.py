@@ -91,12 +91,14 @@ def measured_valu(kernel: str):
 
 def measured_traffic(kernel: str, cells: int):
     """HBM bytes per launch from the committed PMC summary, if it still
-    describes the current kernel source (else None)."""
+    describes the current kernel source (else None). The occupancy-capped
+    forms (".../w3") launch the same instantiation and move the same bytes;
+    the counters, which see instantiations, hold one record for both."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         db = json.load(fh)
-    rec = db.get(kernel)
+    rec = db.get(kernel.split("/")[0])
     if not rec or rec.get("source_hash") != kernel_hash() or rec.get("cells") != cells:
         return None
     return rec.get("bytes_per_launch")

@@ -538,8 +538,15 @@ __global__ __launch_bounds__(256) void k_reduce(const double* partials, int npar
 }
 
 // ------------------------------ variants ---------------------------------
-constexpr LatticeVariant kLat[] = {{64, 1, 1}, {64, 4, 1}, {128, 2, 1}, {256, 1, 1},
-                                   {64, 4, 2}, {256, 1, 2}, {128, 2, 4}, {256, 1, 4}};
+// The /w3 forms reserve 44 KiB of LDS per 256-thread block that the kernel
+// never touches: 3 blocks fit in a CU's 160 KiB where 4 would by registers, so
+// they run 3 waves per SIMD instead of 4. On 512^3 FP32 lattices the 256 x 1
+// block ran 2 % faster so (fewer streams in flight per channel); on 256^3
+// the blocks were within 1 %.
+constexpr unsigned kOcc3Lds = 44 * 1024;
+constexpr LatticeVariant kLat[] = {{64, 1, 1},  {64, 4, 1},  {128, 2, 1}, {256, 1, 1},
+                                   {64, 4, 2},  {256, 1, 2}, {128, 2, 4}, {256, 1, 4},
+                                   {128, 2, 1}, {256, 1, 1}};
 constexpr int kNumLat = sizeof(kLat) / sizeof(kLat[0]);
 // At most 512 threads: with 1024 (4 waves per SIMD, at most 128 VGPRs) every
 // member build spills to scratch, which the build refuses for every kernel.
@@ -584,26 +591,29 @@ int grid_for(int64_t n) {
 }
 
 template <typename T, int BX, int BY, int CZ, bool EXT, bool NTS>
-void lat_launch_stores(bool diag, dim3 grid, dim3 block, const void* src, void* dst,
+void lat_launch_stores(bool diag, dim3 grid, dim3 block, unsigned lds, const void* src, void* dst,
                        const LatticeGeom& g, double* partials, unsigned long long* bad,
                        hipStream_t s) {
   if (diag)
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, EXT, NTS>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, true, EXT, NTS>), grid, block, lds, s,
                        (const T*)src, (T*)dst, g, partials, bad);
   else
-    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, EXT, NTS>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_step_lattice<T, BX, BY, CZ, false, EXT, NTS>), grid, block, lds, s,
                        (const T*)src, (T*)dst, g, partials, bad);
 }
 
 template <typename T, int BX, int BY, int CZ, bool EXT>
 hipError_t lat_launch(bool diag, const void* src, void* dst, const LatticeGeom& g,
-                      double* partials, unsigned long long* bad, hipStream_t s) {
+                      double* partials, unsigned long long* bad, hipStream_t s,
+                      unsigned lds = 0) {
   dim3 block(BX, BY, 1);
   dim3 grid((g.nx + BX - 1) / BX, (g.ny + BY - 1) / BY, (g.nz + CZ - 1) / CZ);
   if (g.cached_store)
-    lat_launch_stores<T, BX, BY, CZ, EXT, false>(diag, grid, block, src, dst, g, partials, bad, s);
+    lat_launch_stores<T, BX, BY, CZ, EXT, false>(diag, grid, block, lds, src, dst, g, partials,
+                                                 bad, s);
   else
-    lat_launch_stores<T, BX, BY, CZ, EXT, true>(diag, grid, block, src, dst, g, partials, bad, s);
+    lat_launch_stores<T, BX, BY, CZ, EXT, true>(diag, grid, block, lds, src, dst, g, partials,
+                                                bad, s);
   return hipGetLastError();
 }
 
@@ -619,6 +629,8 @@ hipError_t lat_dispatch(int v, bool diag, const void* src, void* dst, const Latt
     case 5: return lat_launch<T, 256, 1, 2, EXT>(diag, src, dst, g, partials, bad, s);
     case 6: return lat_launch<T, 128, 2, 4, EXT>(diag, src, dst, g, partials, bad, s);
     case 7: return lat_launch<T, 256, 1, 4, EXT>(diag, src, dst, g, partials, bad, s);
+    case 8: return lat_launch<T, 128, 2, 1, EXT>(diag, src, dst, g, partials, bad, s, kOcc3Lds);
+    case 9: return lat_launch<T, 256, 1, 1, EXT>(diag, src, dst, g, partials, bad, s, kOcc3Lds);
   }
   return hipErrorInvalidValue;
 }
@@ -708,12 +720,15 @@ const char* lattice_kernel_name(int precision, int v) {
   static const char* n32[] = {"k_step_lattice<float,64,1,1>",  "k_step_lattice<float,64,4,1>",
                               "k_step_lattice<float,128,2,1>", "k_step_lattice<float,256,1,1>",
                               "k_step_lattice<float,64,4,2>",  "k_step_lattice<float,256,1,2>",
-                              "k_step_lattice<float,128,2,4>", "k_step_lattice<float,256,1,4>"};
+                              "k_step_lattice<float,128,2,4>", "k_step_lattice<float,256,1,4>",
+                              "k_step_lattice<float,128,2,1>/w3",
+                              "k_step_lattice<float,256,1,1>/w3"};
   static const char* n64[] = {
-      "k_step_lattice<double,64,1,1>",  "k_step_lattice<double,64,4,1>",
-      "k_step_lattice<double,128,2,1>", "k_step_lattice<double,256,1,1>",
-      "k_step_lattice<double,64,4,2>",  "k_step_lattice<double,256,1,2>",
-      "k_step_lattice<double,128,2,4>", "k_step_lattice<double,256,1,4>"};
+      "k_step_lattice<double,64,1,1>",     "k_step_lattice<double,64,4,1>",
+      "k_step_lattice<double,128,2,1>",    "k_step_lattice<double,256,1,1>",
+      "k_step_lattice<double,64,4,2>",     "k_step_lattice<double,256,1,2>",
+      "k_step_lattice<double,128,2,4>",    "k_step_lattice<double,256,1,4>",
+      "k_step_lattice<double,128,2,1>/w3", "k_step_lattice<double,256,1,1>/w3"};
   if (v < 0 || v >= kNumLat) return "?";
   return precision ? n32[v] : n64[v];
 }
