@@ -233,8 +233,10 @@ rlb_status rlb_grad(rlb_handle h, const double* dL_du, const double* dL_deps,
                     double dL_dtau[3], double* dL_deps0, double* dL_du0,
                     int32_t io_on_device);
 
-/* Kernel variants (block shape x cells per thread) of the path this handle
- * dispatches to. rlb_tune times every variant with HIP events on trial steps
+/* Kernel variants (block shape x cells per thread; for the lattice step also
+ * the waves per SIMD: a name ending in "/w3" reserves unused LDS so that 3
+ * waves per SIMD run instead of 4; for round kernels the steps per launch,
+ * "/hH") of the path this handle dispatches to. rlb_tune times every variant with HIP events on trial steps
  * that read the current state and write only the spare buffer (the state is
  * unchanged), selects the fastest, and returns all timings (ms per step,
  * host array of rlb_num_variants doubles, may be NULL). */
