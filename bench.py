@@ -698,6 +698,67 @@ def error_vs_oracle(torch, rlb, prob, st, steps: int, kernels, diag_every: int):
     return out
 
 
+def adjoint_trace(csv_path: str, command: str, grid: str = "512x512x1",
+                  steps: int = 1000) -> str:
+    """Markdown summary of the reverse sweeps in a rocprofv3 kernel trace of
+    the adjoint form: launches and durations of the reverse step (k_adj_step)
+    and the recomputation (k_gstep) on one lattice's grid, how many reverse
+    steps a recomputation kernel overlapped in time, and per sweep the span
+    against the sum of its kernels' durations (a sweep: `steps` consecutive
+    reverse steps, one gradient of a run of that many steps)."""
+    import csv
+    import statistics
+
+    rows = []
+    for r in csv.DictReader(open(csv_path)):
+        name = r["Kernel_Name"]
+        kind = "adj" if "k_adj_step" in name else ("g" if "k_gstep" in name else None)
+        if kind is None or "x".join(r[f"Grid_Size_{a}"] for a in "XYZ") != grid:
+            continue
+        rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), kind))
+    rows.sort()
+    adj = [(s, e) for s, e, k in rows if k == "adj"]
+    rec = [(s, e) for s, e, k in rows if k == "g"]
+    out = [f"Command: `{command}`", ""]
+    if not adj:
+        return "\n".join(out + [f"No reverse steps on the {grid} grid.", ""])
+    # sweeps (one per gradient): consecutive runs of `steps` reverse steps
+    sweeps = [adj[i:i + steps] for i in range(0, len(adj), steps)]
+    overlapped, j = 0, 0
+    for s, e in adj:
+        while j < len(rec) and rec[j][1] < s:
+            j += 1
+        k = j
+        while k < len(rec) and rec[k][0] < e:
+            if rec[k][1] > s:
+                overlapped += 1
+                break
+            k += 1
+
+    def stat(v):
+        us = [(e - s) / 1e3 for s, e in v]
+        return len(us), statistics.mean(us), statistics.median(us)
+
+    na, ma, da = stat(adj)
+    ng, mg, dg = stat(rec) if rec else (0, 0.0, 0.0)
+    out += [f"Kernels on the {grid} grid:", "",
+            "| kernel | launches | mean (us) | median (us) |", "|---|---|---|---|",
+            f"| `k_adj_step` (reverse step) | {na} | {ma:.2f} | {da:.2f} |",
+            f"| `k_gstep` (recomputation) | {ng} | {mg:.2f} | {dg:.2f} |", "",
+            f"Reverse steps overlapped in time by a recomputation kernel: {overlapped} of {na} "
+            f"({100.0 * overlapped / na:.1f} %).", "",
+            "| sweep | reverse steps | span (ms) | reverse-step time (ms) | recomputation time "
+            "within the span (ms) | span / sum of both |", "|---|---|---|---|---|---|"]
+    for i, sw in enumerate(sweeps):
+        s0, s1 = sw[0][0], sw[-1][1]
+        ta = sum(e - s for s, e in sw) / 1e6
+        tg = sum(min(e, s1) - max(s, s0) for s, e in rec if e > s0 and s < s1) / 1e6
+        span = (s1 - s0) / 1e6
+        out.append(f"| {i} | {len(sw)} | {span:.2f} | {ta:.2f} | {tg:.2f} | "
+                   f"{span / (ta + tg):.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def summarize_trace(csv_path: str, command: str, top: int = 25, min_launches: int = 40) -> str:
     """Markdown tables of a rocprofv3 --kernel-trace --stats run: the
     kernel_stats.csv summary, and (from the kernel_trace.csv beside it) the
@@ -968,6 +1029,8 @@ def main():
                     help="fuse the FP64 conservation sums into every N-th step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
+    ap.add_argument("--adjoint-trace", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
+                    help="summarise the reverse sweeps in a rocprofv3 kernel_trace.csv")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--valu-summary", nargs=2, metavar=("CSV", "COMMAND"),
@@ -982,6 +1045,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(*args.summarize_trace), end="")
+        return
+    if args.adjoint_trace:
+        print(adjoint_trace(*args.adjoint_trace), end="")
         return
     if args.oracle_sweep:
         print(json.dumps(cpu_baseline_sweep()), flush=True)

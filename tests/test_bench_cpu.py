@@ -151,3 +151,30 @@ def test_more_than_one_gpu_is_refused_before_any_device_work():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr and "--gpus 2" in r.stderr
     assert r.stdout == ""
+
+
+def test_adjoint_trace_summary(tmp_path):
+    """Reverse steps, recomputation kernels, their overlap and the sweeps of
+    a synthetic kernel trace (two sweeps, every other step overlapped)."""
+    import csv
+    p = tmp_path / "run_kernel_trace.csv"
+    with open(p, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kernel_Name", "Start_Timestamp", "End_Timestamp",
+                    "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"])
+        t = 0
+        for i in range(10):
+            w.writerow(["void rlb::k_adj_step<float, true>(x)", t, t + 15000, 512, 512, 1])
+            if i % 2 == 0:
+                w.writerow(["void rlb::k_gstep<float>(x)", t + 5000, t + 14000, 512, 512, 1])
+            t += 16000
+        w.writerow(["void rlb::k_adj_step<float, true>(x)", 0, 1, 64, 64, 1])  # other grid
+        t += 5_000_000
+        for i in range(5):
+            w.writerow(["void rlb::k_adj_step<float, true>(x)", t, t + 15000, 512, 512, 1])
+            t += 15500
+    md = bench.adjoint_trace(str(p), "cmd", steps=10)
+    assert "| `k_adj_step` (reverse step) | 15 | 15.00 | 15.00 |" in md
+    assert "| `k_gstep` (recomputation) | 5 | 9.00 | 9.00 |" in md
+    assert "5 of 15 (33.3 %)" in md
+    assert "| 0 | 10 |" in md and "| 1 | 5 |" in md
