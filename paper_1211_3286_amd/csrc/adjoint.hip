@@ -148,6 +148,37 @@ __device__ __forceinline__ void gather_adjoint(const T* __restrict__ adj, int64_
   }
 }
 
+// One DPP exchange of a double between the lanes of a row of 16 (CTRL a
+// permutation within the row, so every lane receives a value).
+template <int CTRL>
+__device__ __forceinline__ double dpp_row(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum of a double over the 64 lanes of a wave (all lanes active), uniform in
+// the wave: four DPP exchanges make every lane of a row of 16 hold the row's
+// sum (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror), then the four row sums are read out. VALU work only: no LDS
+// round trips, which matter when every wave of a single-round launch reduces
+// at the same time.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_row<0xB1>(v);
+  v += dpp_row<0x4E>(v);
+  v += dpp_row<0x141>(v);
+  v += dpp_row<0x140>(v);
+  return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+}
+
 // g-only forward step between g-plane buffers (recomputation of a segment).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gstep(const T* __restrict__ src, T* __restrict__ dst,
@@ -196,7 +227,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
                                                   T* __restrict__ adj_out, int64_t cs, AdjGeom d,
                                                   double* __restrict__ partials) {
   const uint32_t esz = sizeof(T);
-  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const int x = blockIdx.x * 64 + threadIdx.x;
   const int r = thread_row();
   if (x < d.nx && r < d.ny * d.nz) {
@@ -218,20 +249,30 @@ __global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
 #pragma unroll
       for (int a = 0; a < 19; ++a) gb[a] = adj_in[(int64_t)a * cs + c];
     }
-    double dt[4] = {0.0, 0.0, 0.0, 0.0};
-    adjoint_apply(pr, gb, d.rt, dt);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] += dt[q];
+    adjoint_apply(pr, gb, d.rt, acc);
 #pragma unroll
     for (int a = 0; a < 19; ++a) st(adj_out + (int64_t)a * cs, self, gb[a]);
   }
-  const int tid = threadIdx.y * 64 + threadIdx.x;
-  block_sum5<256>(acc, tid);
-  if (tid == 0)
+  // The block's four dL/dtau sums: one per wave by DPP, then thread 0 adds
+  // the kRows waves' sums into the block's own partials slot.
+  __shared__ double sh[kRows][4];
 #pragma unroll
-    for (int k = 0; k < 5; ++k)
-      partials[(((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 5 + k] +=
-          acc[k];
+  for (int q = 0; q < 4; ++q) acc[q] = wave_sum(acc[q]);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sh[threadIdx.y][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    double* p =
+        partials + (((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kRows; ++w) s += sh[w][q];
+      p[q] += s;
+    }
+  }
 }
 
 // dL/deps0, dL/du0 from the adjoint of the initial state.
