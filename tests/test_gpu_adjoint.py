@@ -50,10 +50,10 @@ CASES = [
     (12, 1, 10, (0, 0, 1), 10, 10, 1.3),
     (5, 7, 3, (1, 0, 1), 7, 3, 0.0),
     (9, 4, 2, (0, 1, 0), 0, 4, 0.0),
-    # planar lattices recompute two steps per launch through 32 x 16 windows:
-    # several windows a side with ragged last ones, clamped and periodic axes,
-    # segments with an odd number of recomputed steps (K = 4: a pair and a
-    # single) and a last partial segment
+    # planar lattices: rows longer than one 64-cell wave with a ragged last
+    # wave, clamped and periodic axes, a last partial segment (T = 11, K = 4;
+    # T = 9, K = 5) and a single segment with nothing recomputed beside the
+    # reverse steps (T = K)
     (70, 37, 1, (1, 0, 0), 11, 4, 0.0),
     (33, 16, 1, (0, 1, 1), 9, 5, 0.0),
     (31, 15, 1, (1, 1, 0), 8, 8, 0.0),
