@@ -65,13 +65,21 @@ __device__ __forceinline__ void decompose(int c, const G& d, int& x, int& y, int
 }
 
 // The step kernels' geometry: each wave takes 64 consecutive x-cells of one
-// row (y, z), a block kRows rows, one cell per thread (the grid's y and z
-// count blocks of rows). The row index is uniform in a wave, so (y, z) come
-// from a scalar division and no cell index is divided; with no loop over
-// cells the reverse step fits 115 VGPRs (4 waves per SIMD: a 512 x 512 step
-// in one round of waves).
+// row (y, z), a block kRows rows, one cell per thread. The row index is
+// uniform in a wave, so (y, z) come from a scalar division and no cell index
+// is divided; with no loop over cells the reverse step fits 101 VGPRs (4
+// waves per SIMD: a 512 x 512 step in one round of waves).
 constexpr int kRows = 4;
 constexpr int64_t kMaxGridY = 65535;
+
+// The 8 XCDs of the chip take the blocks of a launch in turn (block b on XCD
+// b mod 8), each XCD behind its own L2. The kernels renumber their blocks so
+// that each XCD takes one contiguous run of row blocks, a band of whole rows
+// whose y neighbours it pulls mostly through its own L2. Taken as launched,
+// the 8 blocks of a 512-cell row went to 8 XCDs: each XCD kept a 64-cell
+// column strip of the lattice, and the x neighbours at both edges of every
+// strip came through lines that another XCD fetched too.
+constexpr unsigned kXcds = 8;
 
 dim3 row_grid(const AdjGeom& g) {
   const int64_t rows = (int64_t)g.ny * g.nz;
@@ -85,10 +93,17 @@ int64_t row_blocks(const AdjGeom& g) {
   return (int64_t)r.x * r.y * r.z;
 }
 
-// The row of this thread (uniform in its wave).
-__device__ __forceinline__ int thread_row() {
-  return __builtin_amdgcn_readfirstlane(
-      (int)((blockIdx.z * gridDim.y + blockIdx.y) * kRows + threadIdx.y));
+// This thread's cell: x, and its row r = y + ny z (uniform in its wave).
+// Launched block b, on XCD j = b mod 8, is the (b / 8)-th of that XCD's run
+// of logical blocks: XCD j takes q + (j < rem) of the nb = 8q + rem blocks,
+// starting at jq + min(j, rem). The renumbering is one to one for any nb.
+__device__ __forceinline__ void row_cell(int& x, int& r) {
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const unsigned j = b % kXcds, q = nb / kXcds, rem = nb % kXcds;
+  const unsigned lb = j * q + (j < rem ? j : rem) + b / kXcds;
+  x = (int)((lb % gridDim.x) * 64 + threadIdx.x);
+  r = __builtin_amdgcn_readfirstlane((int)((lb / gridDim.x) * kRows + threadIdx.y));
 }
 
 // Cells y with src(y, e) = c along one axis (the pull source is y - e,
@@ -184,8 +199,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gstep(const T* __restrict__ src, T* __restrict__ dst,
                                                int64_t cs, AdjGeom d) {
   const uint32_t esz = sizeof(T);
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int r = thread_row();
+  int x, r;
+  row_cell(x, r);
   if (x < d.nx && r < d.ny * d.nz) {
     const int y = r % d.ny, z = r / d.ny;
     uint32_t off[19], self;
@@ -228,8 +243,8 @@ __global__ __launch_bounds__(256) void k_adj_step(const T* __restrict__ state,
                                                   double* __restrict__ partials) {
   const uint32_t esz = sizeof(T);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int r = thread_row();
+  int x, r;
+  row_cell(x, r);
   if (x < d.nx && r < d.ny * d.nz) {
     const int y = r % d.ny, z = r / d.ny;
     uint32_t off[19], self;
