@@ -759,6 +759,52 @@ def adjoint_trace(csv_path: str, command: str, grid: str = "512x512x1",
     return "\n".join(out) + "\n"
 
 
+def adjoint_traffic(fetch_csv: str, write_csv: str, command: str, cells: int = 512 * 512) -> str:
+    """Markdown table of the HBM bytes per dispatch of the reverse-sweep
+    kernels on a lattice of `cells` cells (one thread per cell), from one
+    FETCH_SIZE and one WRITE_SIZE rocprofv3 --pmc run of the adjoint form with
+    --copy-calibration: each counter scaled by what it reads for the 1 GiB
+    copy in the same run, set against the algorithmic bytes (reverse step:
+    19 taped populations and 19 adjoint populations read, 19 written, 228 B
+    per cell in FP32; recomputation: 19 read, 19 written, 152 B)."""
+    import collections
+    import csv
+
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"^.*::(?=k_)", "", name.split("(")[0])
+
+    vals = collections.defaultdict(list)
+    copy = {}
+    for path in (fetch_csv, write_csv):
+        for r in csv.DictReader(open(path)):
+            k, g, c = r["Kernel_Name"], int(r["Grid_Size"]), r["Counter_Name"]
+            v = float(r["Counter_Value"]) * 1024.0
+            if "copyBuffer" in k:
+                copy.setdefault(c, []).append(v)
+            elif g == cells and short(k).startswith(("k_adj_step", "k_gstep")):
+                vals[(short(k), c)].append(v)
+    # the 1 GiB copy: the largest copy dispatches (the tape's checkpoints are
+    # copies of one state, far smaller)
+    big = {c: [x for x in v if x > 0.5 * max(v)] for c, v in copy.items()}
+    scale = {c: (1 << 30) / (sum(v) / len(v)) for c, v in big.items()}
+    out = [f"Command: `{command}`", "",
+           f"Copy calibration (1 GiB): FETCH_SIZE x {scale.get('FETCH_SIZE', float('nan')):.4f}, "
+           f"WRITE_SIZE x {scale.get('WRITE_SIZE', float('nan')):.4f}.", "",
+           "| kernel | dispatches | fetch B / dispatch | write B / dispatch | total / algorithmic |",
+           "|---|---|---|---|---|"]
+    for name in sorted({k for k, _ in vals}):
+        f, w = vals.get((name, "FETCH_SIZE")), vals.get((name, "WRITE_SIZE"))
+        if not f or not w or "FETCH_SIZE" not in scale or "WRITE_SIZE" not in scale:
+            continue
+        esz = 8 if "double" in name else 4
+        alg = (57 if name.startswith("k_adj_step") else 38) * esz * cells
+        fb = sum(f) / len(f) * scale["FETCH_SIZE"]
+        wb = sum(w) / len(w) * scale["WRITE_SIZE"]
+        out.append(f"| `{name}` | {len(f)} | {fb:.4e} | {wb:.4e} | {(fb + wb) / alg:.4f} |")
+    return "\n".join(out) + "\n"
+
+
 def summarize_trace(csv_path: str, command: str, top: int = 25, min_launches: int = 40) -> str:
     """Markdown tables of a rocprofv3 --kernel-trace --stats run: the
     kernel_stats.csv summary, and (from the kernel_trace.csv beside it) the
@@ -1031,6 +1077,9 @@ def main():
                     help="also run a plain 1 GiB device copy (scale for HBM byte counters)")
     ap.add_argument("--adjoint-trace", nargs=2, metavar=("TRACE_CSV", "COMMAND"),
                     help="summarise the reverse sweeps in a rocprofv3 kernel_trace.csv")
+    ap.add_argument("--adjoint-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="print the HBM bytes per dispatch of the reverse-sweep kernels from two "
+                         "PMC runs of the adjoint form and exit")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("CSV", "COMMAND"),
                     help="print a markdown summary of a rocprofv3 kernel_stats.csv and exit")
     ap.add_argument("--valu-summary", nargs=2, metavar=("CSV", "COMMAND"),
@@ -1048,6 +1097,9 @@ def main():
         return
     if args.adjoint_trace:
         print(adjoint_trace(*args.adjoint_trace), end="")
+        return
+    if args.adjoint_traffic:
+        print(adjoint_traffic(*args.adjoint_traffic), end="")
         return
     if args.oracle_sweep:
         print(json.dumps(cpu_baseline_sweep()), flush=True)

@@ -178,3 +178,41 @@ def test_adjoint_trace_summary(tmp_path):
     assert "| `k_gstep` (recomputation) | 5 | 9.00 | 9.00 |" in md
     assert "5 of 15 (33.3 %)" in md
     assert "| 0 | 10 |" in md and "| 1 | 5 |" in md
+
+
+def test_adjoint_traffic_summary(tmp_path):
+    """Byte counters of a synthetic PMC pair: the copy sets the scale, only
+    the reverse-sweep kernels on the lattice's grid are priced, against 57
+    (reverse step) and 38 (recomputation) FP32 values per cell."""
+    import csv
+    cells = 4096
+    rows = {"FETCH_SIZE": [], "WRITE_SIZE": []}
+    # copy: 1 GiB each way, counters read half (fetch) and all (write)
+    rows["FETCH_SIZE"].append(("copyBuffer", 131072, (1 << 30) / 2 / 1024))
+    rows["WRITE_SIZE"].append(("copyBuffer", 131072, (1 << 30) / 1024))
+    # a checkpoint copy of one state does not count towards the calibration
+    rows["FETCH_SIZE"].append(("copyBuffer", 131072, 1e3))
+    rows["WRITE_SIZE"].append(("copyBuffer", 131072, 1e3))
+    adj = "void rlb::(anonymous namespace)::k_adj_step<float, true>(float const*, float*)"
+    gst = "void rlb::(anonymous namespace)::k_gstep<float>(float const*, float*)"
+    for _ in range(3):
+        rows["FETCH_SIZE"].append((adj, cells, 38 * 4 * cells / 2 / 1024))
+        rows["WRITE_SIZE"].append((adj, cells, 19 * 4 * cells * 1.1 / 1024))
+        rows["FETCH_SIZE"].append((gst, cells, 19 * 4 * cells / 2 / 1024))
+        rows["WRITE_SIZE"].append((gst, cells, 19 * 4 * cells / 1024))
+    rows["FETCH_SIZE"].append((gst, 64, 1e9))  # another grid
+    rows["WRITE_SIZE"].append((gst, 64, 1e9))
+    paths = []
+    for c, rs in rows.items():
+        p = tmp_path / f"{c}.csv"
+        with open(p, "w", newline="") as fh:
+            w = csv.writer(fh)
+            w.writerow(["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+            for k, g, v in rs:
+                w.writerow([k, g, c, v])
+        paths.append(str(p))
+    md = bench.adjoint_traffic(paths[0], paths[1], "cmd", cells=cells)
+    assert "FETCH_SIZE x 2.0000, WRITE_SIZE x 1.0000" in md
+    # (38 + 19 * 1.1) / 57 = 1.0333
+    assert "| `k_adj_step<float, true>` | 3 | 6.2259e+05 | 3.4243e+05 | 1.0333 |" in md
+    assert "| `k_gstep<float>` | 3 | 3.1130e+05 | 3.1130e+05 | 1.0000 |" in md
