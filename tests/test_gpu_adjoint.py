@@ -76,6 +76,24 @@ def test_fp64_adjoint_matches_oracle(case):
     assert relmax(g_u0, o_u0) < 1e-10
 
 
+def test_fp64_adjoint_matches_oracle_two_layers_of_row_blocks():
+    """520 x 520 rows of 2 cells: 67,600 blocks of 4 rows exceed the 65,535 a
+    grid's y holds, so the launches take two z layers of row blocks (131,070
+    blocks, not a multiple of the 8 XCDs, the second layer mostly past the
+    last row). Every cell must still be taken exactly once by the kernels'
+    block renumbering."""
+    prob = wl.random_modes(2, 520, 520, seed=11, umax=0.2, amp=0.1, tau_v=0.8, tau_e=0.6,
+                           tau_eps=0.7, tau_f=0.8, bc=(0, 1, 0))
+    du, de = _cotangents(prob)
+    say("adjoint fp64 2x520x520 T3 K2 (two z layers of row blocks)")
+    g_tau, g_e0, g_u0 = _gpu_grad(prob, 3, 2, FP64, du, de)
+    o_tau, o_e0, o_u0 = oracle.grad(prob, 3, du, de)
+    say("  tau gpu", g_tau, "oracle", o_tau)
+    assert relmax(g_tau, o_tau) < 1e-10
+    assert relmax(g_e0, o_e0) < 1e-10
+    assert relmax(g_u0, o_u0) < 1e-10
+
+
 def test_fp32_adjoint_matches_oracle_64x64():
     prob = wl.shear_vortex(64, seed=1212)
     T, K = 100, 50
