@@ -333,14 +333,15 @@ def bench_blast(torch, rlb, wl, L: int = 512, steps: int = 400, warmup: int = 10
 
 
 def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
-                  oracle_L: int = 64, oracle_steps: int = 200):
+                  oracle_L: int = 64, oracle_steps: int = 200, grad_reps: int = 5):
     """The adjoint form on the L x L x 1 shear-wave/vortex field, FP32, with
     checkpoints every K steps. The loss is the L2 mismatch of the final u and
     eps with a target made by the same model (FP64) at seeded perturbed
     relaxation times plus 1 % noise. Times (HIP events on the handle's
-    stream): the taped forward, and the gradient (rlb_grad) after one untimed
-    call that instantiates its graph. Errors: dL/dtau against central finite
-    differences of the FP64 forward (h = 1e-4), over max(|FD|, |grad|); and
+    stream): the taped forward, and the gradient (rlb_grad): the median of
+    grad_reps calls after one untimed call that instantiates its graph.
+    Errors: dL/dtau against central finite differences of the FP64 forward
+    (h = 1e-4), over max(|FD|, |grad|); and
     every output against the oracle's FP64 adjoint on the oracle_L^2 instance,
     oracle_steps steps."""
     import copy
@@ -387,13 +388,16 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
     t0 = time.perf_counter()
     sim.grad(du, de)  # builds and instantiates the reverse sweep's graph
     first_s = time.perf_counter() - t0
-    torch.cuda.synchronize()
-    ev[2].record(stream)
-    dtau, de0, du0 = sim.grad(du, de)
-    ev[3].record(stream)
-    torch.cuda.synchronize()
+    grad_runs = []
+    for _ in range(grad_reps):
+        torch.cuda.synchronize()
+        ev[2].record(stream)
+        dtau, de0, du0 = sim.grad(du, de)
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        grad_runs.append(ev[2].elapsed_time(ev[3]))
     fwd_ms = ev[0].elapsed_time(ev[1])
-    grad_ms = ev[2].elapsed_time(ev[3])
+    grad_ms = float(np.median(grad_runs))
     sim.close()
     h = 1e-4
     fd = []
@@ -423,6 +427,7 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
     total_ms = fwd_ms + grad_ms
     return {"lattice": f"{L}x{L}x1", "steps": steps, "ckpt_every": K,
             "forward_ms": fwd_ms, "gradient_ms": grad_ms,
+            "gradient_ms_runs": [round(x, 4) for x in grad_runs],
             "gradient_first_call_s": first_s,
             "cell_steps_per_s": cell_steps / (total_ms * 1e-3),
             "bytes_per_cell_step": 684,
