@@ -1175,10 +1175,11 @@ def main():
             log(name, forms[name])
     if want("copy_ceiling"):
         # the runtime's own device-to-device copy of the bytes one FP32 step
-        # moves (38 x 4 B per cell read, the same written): a practical
-        # bandwidth ceiling to read the roofline fraction against
+        # moves (38 x 4 B per cell read, the same written), as context for the
+        # step's rate: step_speed_over_copy is a ratio of speeds, not a
+        # fraction of a peak (the fused step moves its bytes faster than it)
         cc = copy_calibration(torch, nbytes=38 * 4 * head["cells"], reps=20)
-        cc["step_fraction_of_copy"] = head["achieved_gbs"] / cc["gbs"]
+        cc["step_speed_over_copy"] = head["achieved_gbs"] / cc["gbs"]
         forms["copy_ceiling"] = cc
         log("copy ceiling", cc)
     if args.copy_calibration:
