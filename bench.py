@@ -338,7 +338,8 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
     checkpoints every K steps. The loss is the L2 mismatch of the final u and
     eps with a target made by the same model (FP64) at seeded perturbed
     relaxation times plus 1 % noise. Times (HIP events on the handle's
-    stream): the taped forward, and the gradient (rlb_grad): the median of
+    stream): the taped forward in the autotuned step variant, and the
+    gradient (rlb_grad): the median of
     grad_reps calls after one untimed call that instantiates its graph.
     Errors: dL/dtau against central finite differences of the FP64 forward
     (h = 1e-4), over max(|FD|, |grad|); and
@@ -375,6 +376,7 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
         return float(((u - ut) ** 2).sum() + ((e - et) ** 2).sum())
 
     sim = rlb.from_problems(prob, precision=rlb.FP32, ckpt_every=K, tape_steps=steps)
+    fwd_kernel = sim.tune()["name"]  # trial steps leave the state as it was
     stream = sim.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     torch.cuda.synchronize()
@@ -426,7 +428,7 @@ def bench_adjoint(torch, rlb, wl, L: int = 512, steps: int = 1000, K: int = 50,
     cell_steps = nc * steps
     total_ms = fwd_ms + grad_ms
     return {"lattice": f"{L}x{L}x1", "steps": steps, "ckpt_every": K,
-            "forward_ms": fwd_ms, "gradient_ms": grad_ms,
+            "forward_ms": fwd_ms, "forward_kernel": fwd_kernel, "gradient_ms": grad_ms,
             "gradient_ms_runs": [round(x, 4) for x in grad_runs],
             "gradient_first_call_s": first_s,
             "cell_steps_per_s": cell_steps / (total_ms * 1e-3),
