@@ -73,12 +73,12 @@ constexpr int kRows = 4;
 constexpr int64_t kMaxGridY = 65535;
 
 // The 8 XCDs of the chip take the blocks of a launch in turn (block b on XCD
-// b mod 8), each XCD behind its own L2. The kernels renumber their blocks so
-// that each XCD takes one contiguous run of row blocks, a band of whole rows
-// whose y neighbours it pulls mostly through its own L2. Taken as launched,
-// the 8 blocks of a 512-cell row went to 8 XCDs: each XCD kept a 64-cell
-// column strip of the lattice, and the x neighbours at both edges of every
-// strip came through lines that another XCD fetched too.
+// b mod 8), each XCD behind its own L2. Taken as launched, the 8 blocks of a
+// 512-cell row went to 8 XCDs: each XCD kept a 64-cell column strip, and the
+// line at each edge of a strip, which the x-shifted pulls of the waves on
+// both sides share, was fetched by two XCDs. The kernels renumber their
+// blocks so that each XCD takes one contiguous run of row blocks, a band of
+// whole rows: no row is split over XCDs.
 constexpr unsigned kXcds = 8;
 
 dim3 row_grid(const AdjGeom& g) {
